@@ -1,0 +1,278 @@
+"""CPU reference ("oracle") for the linearized-implicit thermochemistry of
+SFUMATO# (arXiv 2604.21438) -- Python access through ctypes.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package.  It shares no
+code with the HIP implementation in ``paper_2604_21438_amd``.
+
+The arithmetic lives in ``orc_chem.cpp`` (plain serial C++, binary64,
+-ffp-contract=off).  ``build()`` compiles two libraries next to this file:
+``liborc.so`` (plain) and ``liborc_count.so`` (counting build, used for the
+algorithmic operation count per cell-update).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liborc.so")
+LIB_COUNT = os.path.join(HERE, "liborc_count.so")
+SRC = os.path.join(HERE, "orc_chem.cpp")
+
+NREAC, NPROC, NLINE = 12, 14, 5
+IR_FIXED, IR_EVOLVE = 0, 1
+THERMAL_EVOLVE, THERMAL_ISOTHERMAL = 0, 1
+DUST_EVOLVE, DUST_FROZEN = 0, 1
+F_CAP, F_TIGHT, F_NOCONV, F_INVALID, F_FLOOR, F_NRFAIL = 1, 2, 4, 8, 16, 32
+
+CFLAGS = ["-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+          "-shared", "-Wall", "-pthread"]
+
+
+def build(force: bool = True) -> None:
+    """Compile the plain and the counting oracle libraries (g++)."""
+    for out, extra in ((LIB, []), (LIB_COUNT, ["-DORC_COUNT"])):
+        if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(SRC):
+            continue
+        tmp = out + ".tmp"
+        subprocess.check_call(["g++", *CFLAGS, *extra, "-o", tmp, SRC])
+        os.replace(tmp, out)
+
+
+class Network(C.Structure):
+    _fields_ = [
+        ("reac_mult", C.c_double * NREAC),
+        ("proc_mult", C.c_double * NPROC),
+        ("sigma_euv", C.c_double), ("k10_per_g0", C.c_double),
+        ("g0_photon_density", C.c_double), ("zeta_cr", C.c_double),
+        ("k4_pre", C.c_double), ("k4_theta", C.c_double),
+        ("heat_euv_ev", C.c_double), ("heat_h2diss_ev", C.c_double),
+        ("pe_coef", C.c_double), ("pe_eps", C.c_double),
+        ("kappa_max", C.c_double), ("kappa_tnorm", C.c_double),
+        ("kappa_uv", C.c_double), ("e_fuv_ev", C.c_double), ("e_euv_ev", C.c_double),
+        ("x_c", C.c_double), ("x_o", C.c_double), ("f_oiii", C.c_double),
+        ("line_tul", C.c_double * NLINE), ("line_a", C.c_double * NLINE),
+        ("line_g", C.c_double * NLINE), ("line_qn", C.c_double * NLINE),
+        ("line_qe100", C.c_double * NLINE),
+    ]
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("f_chem", C.c_double), ("y_abs", C.c_double), ("newton_rtol", C.c_double),
+        ("c_red", C.c_double), ("t_cmb", C.c_double), ("y_he", C.c_double),
+        ("gamma_ad", C.c_double), ("dust_cap", C.c_double), ("z_default", C.c_double),
+        ("n_cyc", C.c_int32), ("n_sub_max", C.c_int32), ("newton_max", C.c_int32),
+        ("ir_mode", C.c_int32), ("thermal_mode", C.c_int32), ("dust_mode", C.c_int32),
+    ]
+
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_up = C.POINTER(C.c_uint32)
+
+
+class Cells(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64),
+        ("y_h2", _dp), ("y_e", _dp), ("eint", _dp), ("tdust", _dp), ("eir", _dp),
+        ("y_h", _dp), ("y_hp", _dp), ("y_hm", _dp), ("tgas", _dp),
+        ("nh", _dp), ("n_euv", _dp), ("n_fuv", _dp), ("zmet", _dp),
+        ("nsub", _ip), ("niter", _ip), ("flags", _up),
+    ]
+
+
+_libs: dict = {}
+
+
+def _lib(counting: bool = False):
+    path = LIB_COUNT if counting else LIB
+    if path not in _libs:
+        if not os.path.exists(path):
+            build(force=False)
+        lib = C.CDLL(path)
+        P = C.POINTER
+        lib.orc_network_default.argtypes = [P(Network)]
+        lib.orc_params_default.argtypes = [P(Params)]
+        for name in ("orc_li_step", "orc_nr_step"):
+            f = getattr(lib, name)
+            f.argtypes = [P(Network), P(Params), P(Cells), C.c_double, C.c_int]
+            f.restype = C.c_int
+        lib.orc_rk_reference.argtypes = [P(Network), P(Params), P(Cells), C.c_double, C.c_double]
+        lib.orc_rk_reference.restype = C.c_int
+        lib.orc_rate_coeffs.argtypes = [P(Network), P(Params)] + [C.c_double] * 6 + [_dp, _dp]
+        lib.orc_chem_sources.argtypes = [P(Network), P(Params)] + [C.c_double] * 8 + [_dp, _dp, _dp]
+        lib.orc_dust_system.argtypes = [P(Network), P(Params)] + [C.c_double] * 9 + [_dp, _dp, _dp]
+        lib.orc_count_li_cell.argtypes = [P(Network), P(Params), P(Cells), C.c_int64, C.c_double, _dp]
+        lib.orc_count_li_cell.restype = C.c_int
+        _libs[path] = lib
+    return _libs[path]
+
+
+def default_network(**overrides) -> Network:
+    net = Network()
+    _lib().orc_network_default(C.byref(net))
+    for k, v in overrides.items():
+        _assign(net, k, v)
+    return net
+
+
+def default_params(**overrides) -> Params:
+    p = Params()
+    _lib().orc_params_default(C.byref(p))
+    for k, v in overrides.items():
+        _assign(p, k, v)
+    return p
+
+
+def _assign(obj, k, v):
+    cur = getattr(obj, k)
+    if isinstance(cur, C.Array):
+        for i, x in enumerate(v):
+            cur[i] = x
+    else:
+        setattr(obj, k, v)
+
+
+STATE = ("y_h2", "y_e", "eint", "tdust", "eir")
+INPUTS = ("nh", "n_euv", "n_fuv", "zmet")
+OUT_F = ("y_h", "y_hp", "y_hm", "tgas")
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype)) if a is not None else None
+
+
+def _cells(arrs: dict, n: int):
+    """Build the ctypes SoA view; returns (Cells, keepalive)."""
+    keep = {}
+    c = Cells()
+    c.n = n
+    for k in STATE + INPUTS + OUT_F:
+        a = arrs.get(k)
+        if a is not None:
+            assert a.dtype == np.float64 and a.flags.c_contiguous and a.shape == (n,), k
+        keep[k] = a
+        setattr(c, k, _ptr(a, C.c_double))
+    for k, ct in (("nsub", C.c_int32), ("niter", C.c_int32), ("flags", C.c_uint32)):
+        a = arrs.get(k)
+        keep[k] = a
+        setattr(c, k, _ptr(a, ct))
+    return c, keep
+
+
+def _prepare(cells: dict, ir_mode: int):
+    """Copy the inputs, allocate outputs; returns the dict the oracle writes."""
+    n = int(np.asarray(cells["nh"]).shape[0])
+    out = {}
+    for k in STATE + INPUTS:
+        if k in cells and cells[k] is not None:
+            out[k] = np.ascontiguousarray(cells[k], dtype=np.float64).copy()
+    if ir_mode != IR_EVOLVE:
+        out.pop("eir", None)
+    for k in OUT_F:
+        out[k] = np.empty(n, np.float64)
+    out["nsub"] = np.zeros(n, np.int32)
+    out["niter"] = np.zeros(n, np.int32)
+    out["flags"] = np.zeros(n, np.uint32)
+    return out, n
+
+
+def li_step(cells: dict, dt: float, net: Network | None = None, params: Params | None = None,
+            nthreads: int = 1) -> dict:
+    """LI update of every cell over dt [s]; returns a new dict of arrays."""
+    net = net or default_network()
+    params = params or default_params()
+    out, n = _prepare(cells, params.ir_mode)
+    c, keep = _cells(out, n)
+    rc = _lib().orc_li_step(C.byref(net), C.byref(params), C.byref(c), float(dt), int(nthreads))
+    if rc != 0:
+        raise ValueError("orc_li_step rejected its arguments")
+    return out
+
+
+def nr_step(cells: dict, dt: float, net: Network | None = None, params: Params | None = None,
+            nthreads: int = 1) -> dict:
+    net = net or default_network()
+    params = params or default_params()
+    out, n = _prepare(cells, params.ir_mode)
+    c, keep = _cells(out, n)
+    rc = _lib().orc_nr_step(C.byref(net), C.byref(params), C.byref(c), float(dt), int(nthreads))
+    if rc != 0:
+        raise ValueError("orc_nr_step rejected its arguments")
+    return out
+
+
+def rk_reference(cells: dict, dt: float, net: Network | None = None,
+                 params: Params | None = None, step_frac: float = 1e-3) -> dict:
+    net = net or default_network()
+    params = params or default_params()
+    out, n = _prepare(cells, params.ir_mode)
+    c, keep = _cells(out, n)
+    rc = _lib().orc_rk_reference(C.byref(net), C.byref(params), C.byref(c), float(dt),
+                                 float(step_frac))
+    if rc != 0:
+        raise ValueError("orc_rk_reference rejected its arguments")
+    return out
+
+
+def rate_coeffs(T, tdust, nh=1.0, fd=1.0, n_euv=0.0, n_fuv=0.0, net=None, params=None):
+    """(k[12], dk/dT[12]) at one temperature."""
+    net = net or default_network()
+    params = params or default_params()
+    k = np.zeros(NREAC)
+    dk = np.zeros(NREAC)
+    _lib().orc_rate_coeffs(C.byref(net), C.byref(params), T, tdust, nh, fd, n_euv, n_fuv,
+                           _ptr(k, C.c_double), _ptr(dk, C.c_double))
+    return k, dk
+
+
+def chem_sources(y_h2, y_e, T, tdust, nh, fd=1.0, n_euv=0.0, n_fuv=0.0, net=None, params=None):
+    """((R_H2, R_e, Q), jac[3x3] w.r.t. (y_H2, y_e, T), terms[14])."""
+    net = net or default_network()
+    params = params or default_params()
+    out = np.zeros(3)
+    jac = np.zeros(9)
+    terms = np.zeros(NPROC)
+    _lib().orc_chem_sources(C.byref(net), C.byref(params), y_h2, y_e, T, tdust, nh, fd, n_euv,
+                            n_fuv, _ptr(out, C.c_double), _ptr(jac, C.c_double),
+                            _ptr(terms, C.c_double))
+    return out, jac.reshape(3, 3), terms
+
+
+def dust_system(tg, tdust, eir, nh, fd, ntot, n_euv, n_fuv, h, net=None, params=None):
+    """Appendix C matrix (3x3 over dT_d, dE_IR, dT_g), rhs, (S_d, S_IR, S_g, alpha_g)."""
+    net = net or default_network()
+    params = params or default_params()
+    A = np.zeros(9)
+    rhs = np.zeros(3)
+    src = np.zeros(4)
+    _lib().orc_dust_system(C.byref(net), C.byref(params), tg, tdust, eir, nh, fd, ntot, n_euv,
+                           n_fuv, h, _ptr(A, C.c_double), _ptr(rhs, C.c_double),
+                           _ptr(src, C.c_double))
+    return A.reshape(3, 3), rhs, src
+
+
+def count_li(cells: dict, dt: float, idx, net=None, params=None) -> np.ndarray:
+    """Operation counts (add, mul, div, sqrt, transcendental, cmp) of the LI
+    update for each cell index in idx, from the counting build."""
+    net = net or default_network()
+    params = params or default_params()
+    lib = _lib(counting=True)
+    out, n = _prepare(cells, params.ir_mode)
+    c, keep = _cells(out, n)
+    res = np.zeros((len(idx), 6))
+    buf = np.zeros(6)
+    for j, i in enumerate(idx):
+        # the counting build writes its results into the arrays of `out`;
+        # each cell is counted from its original input state
+        rc = lib.orc_count_li_cell(C.byref(net), C.byref(params), C.byref(c), int(i), float(dt),
+                                   _ptr(buf, C.c_double))
+        if rc != 0:
+            raise RuntimeError("counting build not available")
+        res[j] = buf
+    return res

@@ -1,0 +1,180 @@
+"""Seeded synthetic cell populations for the thermochemistry update.
+
+This module only draws inputs.  It contains none of the update's arithmetic
+and is shared by the HIP path's tests and benchmark and by the CPU
+reference's tests, which must see the same bits.  The paper's own snapshots
+(Bonnor-Ebert collapse, H II region, giant molecular cloud) are not
+available, so these distributions stand in for them.
+
+Every population is a dict of contiguous float64 numpy arrays (SoA):
+
+  nh     H-nuclei number density [cm^-3]
+  n_euv  EUV photon number density [cm^-3]
+  n_fuv  FUV photon number density [cm^-3]
+  zmet   metallicity in solar units (dust-to-gas ratio scales with it)
+  y_h2   H2 abundance per H nucleus
+  y_e    electron abundance per H nucleus
+  eint   gas internal energy density [erg cm^-3]
+  tdust  dust temperature [K]
+
+The internal energy is built from a drawn gas temperature with the ideal-gas
+relation E = k_B n_H (1 - y_H2 + y_e + y_He) T / (gamma - 1), y_He = 0.1,
+gamma = 5/3, so that both implementations read identical bits.
+
+Seeds: numpy PCG64 with SeedSequence(21438 + 100 * i) for population i,
+one spawned child stream per drawn field (fixed order).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+KB = 1.380649e-16
+Y_HE = 0.1
+GAMMA = 5.0 / 3.0
+YR = 3.15576e7            # Julian year [s]
+KYR = 1.0e3 * YR
+
+FIELDS = ("nh", "n_euv", "n_fuv", "zmet", "y_h2", "y_e", "eint", "tdust")
+
+
+def _streams(cfg_index: int, nstreams: int, seed_offset: int = 0):
+    ss = np.random.SeedSequence(21438 + 100 * cfg_index + seed_offset)
+    return [np.random.Generator(np.random.PCG64(s)) for s in ss.spawn(nstreams)]
+
+
+def internal_energy(nh, y_h2, y_e, tgas):
+    """Ideal-gas internal energy density from a temperature (input construction)."""
+    return KB * nh * (1.0 - y_h2 + y_e + Y_HE) * tgas / (GAMMA - 1.0)
+
+
+def _abundances(g_h2, g_hp, n):
+    y_hp = 10.0 ** g_hp.uniform(-8.0, -1.0, n)
+    y_hm = np.full(n, 1.0e-12)
+    y_e = y_hp - y_hm                        # charge neutral
+    y_h2 = 10.0 ** g_h2.uniform(-6.0, -0.3, n)
+    # the upper end of the H2 draw can exceed what H-nuclei conservation
+    # allows; clamp it just inside the feasible range
+    y_h2 = np.minimum(y_h2, 0.5 * (1.0 - y_hp - y_hm) * (1.0 - 1.0e-9))
+    return y_h2, y_e
+
+
+def uniform_population(n: int, cfg_index: int = 0, z_choices=None, seed_offset: int = 0):
+    """Independent cells: log10 n_H ~ U[0,8], log10 T ~ U[1,4], T_d = T,
+    log10 y_H2 ~ U[-6,-0.3], log10 y_H+ ~ U[-8,-1], y_H- = 1e-12, y_e from
+    charge neutrality, log10 N_EUV, log10 N_FUV ~ U[-5,1] independently,
+    Z = 1 or drawn uniformly from z_choices."""
+    g = _streams(cfg_index, 8, seed_offset)
+    nh = 10.0 ** g[0].uniform(0.0, 8.0, n)
+    tg = 10.0 ** g[1].uniform(1.0, 4.0, n)
+    y_h2, y_e = _abundances(g[2], g[3], n)
+    n_euv = 10.0 ** g[4].uniform(-5.0, 1.0, n)
+    n_fuv = 10.0 ** g[5].uniform(-5.0, 1.0, n)
+    if z_choices is None:
+        zmet = np.ones(n)
+    else:
+        zmet = np.asarray(z_choices, np.float64)[g[6].integers(0, len(z_choices), n)]
+    return _pack(nh, n_euv, n_fuv, zmet, y_h2, y_e, tg, tg.copy())
+
+
+def _pack(nh, n_euv, n_fuv, zmet, y_h2, y_e, tg, td):
+    out = dict(nh=nh, n_euv=n_euv, n_fuv=n_fuv, zmet=zmet, y_h2=y_h2, y_e=y_e,
+               eint=internal_energy(nh, y_h2, y_e, tg), tdust=td)
+    return {k: np.ascontiguousarray(v, dtype=np.float64) for k, v in out.items()}
+
+
+# ---- the named workloads ------------------------------------------------
+
+def small_cells():
+    """16^3 = 4096 independent cells, Z = 1, dt = 1 kyr (dust factor 1)."""
+    return uniform_population(4096, cfg_index=0), 1.0 * KYR
+
+
+def grid128(n: int | None = None):
+    """128^3 = 2,097,152 cells, Z in {0.01, 0.1, 1} per cell, dt = 10 kyr.
+    n < 128^3 returns the first n cells of the same draw."""
+    full = 128 ** 3
+    cells = uniform_population(full, cfg_index=1, z_choices=(0.01, 0.1, 1.0))
+    if n is not None and n < full:
+        cells = {k: np.ascontiguousarray(v[:n]) for k, v in cells.items()}
+    return cells, 10.0 * KYR
+
+
+def subsample(cells: dict, m: int, seed: int = 7):
+    """Seeded subset of m cells (sorted indices) and the indices."""
+    n = cells["nh"].shape[0]
+    if m >= n:
+        return cells, np.arange(n)
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+    idx = np.sort(rng.choice(n, size=m, replace=False))
+    return {k: np.ascontiguousarray(v[idx]) for k, v in cells.items()}, idx
+
+
+def _density_tail(g_u, g_n, n, mu=np.log(100.0), sigma=2.0, n_break=1.0e4, n_max=1.0e11,
+                  slope=1.5):
+    """n_H with a log-normal body below n_break and a continuous power-law
+    tail p(n) ~ n^-slope on [n_break, n_max] (pdf in n, joined continuously
+    at n_break), drawn by inverse CDF."""
+    from math import erf, sqrt, log, exp, pi
+    lb = log(n_break)
+    z = (lb - mu) / sigma
+    mass_body = 0.5 * (1.0 + erf(z / sqrt(2.0)))
+    # pdf in n of the log-normal at the break
+    pdf_b = exp(-0.5 * z * z) / (n_break * sigma * sqrt(2.0 * pi))
+    # tail pdf A n^-slope continuous at the break
+    A = pdf_b * n_break ** slope
+    mass_tail = A * (n_break ** (1.0 - slope) - n_max ** (1.0 - slope)) / (slope - 1.0)
+    total = mass_body + mass_tail
+    u = g_u.uniform(0.0, 1.0, n) * total
+    out = np.empty(n)
+    body = u < mass_body
+    # body: invert the normal CDF by drawing a truncated normal in ln n
+    nb = int(body.sum())
+    ln = np.empty(nb)
+    filled = 0
+    while filled < nb:
+        x = g_n.normal(mu, sigma, 2 * (nb - filled) + 16)
+        x = x[x < lb]
+        k = min(nb - filled, x.size)
+        ln[filled:filled + k] = x[:k]
+        filled += k
+    out[body] = np.exp(ln)
+    ut = (u[~body] - mass_body) / A  # = int_{n_b}^{n} x^-s dx
+    base = n_break ** (1.0 - slope) - (slope - 1.0) * ut
+    out[~body] = base ** (1.0 / (1.0 - slope))
+    return out, mass_tail / total
+
+
+def point_source_field(pos, src_pos, amp, h):
+    """sum_s amp_s (h / max(|x - x_s|, h))^2 (photon density, 1/r^2)."""
+    out = np.zeros(pos.shape[0])
+    for s in range(src_pos.shape[0]):
+        d = np.sqrt(((pos - src_pos[s]) ** 2).sum(axis=1))
+        out += amp[s] * (h / np.maximum(d, h)) ** 2
+    return out
+
+
+def grid256(n: int | None = None, side: int = 256):
+    """256^3 cells on the unit cube: n_H log-normal (mu = ln 100, sigma = 2)
+    with an n^-1.5 tail above 1e4 to 1e11 cm^-3, log10 T ~ U[1,4], T_d = T,
+    abundances as the uniform population, 8 point sources at uniform
+    positions giving N_EUV = sum A_s (h/r)^2, A_s ~ logU[1,100] cm^-3 and
+    N_FUV = sum r_s A_s (h/r)^2, r_s ~ logU[1,10]; Z = 1; dt = 10 kyr.
+    n < side^3 returns the first n cells (x-fastest ordering)."""
+    full = side ** 3
+    m = full if n is None else min(n, full)
+    g = _streams(2, 10)
+    nh, _ = _density_tail(g[0], g[1], full)
+    tg = 10.0 ** g[2].uniform(1.0, 4.0, full)
+    y_h2, y_e = _abundances(g[3], g[4], full)
+    src = g[5].uniform(0.0, 1.0, (8, 3))
+    amp = 10.0 ** g[6].uniform(0.0, 2.0, 8)
+    ratio = 10.0 ** g[7].uniform(0.0, 1.0, 8)
+    h = 1.0 / side
+    i = np.arange(m)
+    pos = np.stack([(i % side + 0.5) * h, ((i // side) % side + 0.5) * h,
+                    (i // (side * side) + 0.5) * h], axis=1)
+    n_euv = point_source_field(pos, src, amp, h)
+    n_fuv = point_source_field(pos, src, amp * ratio, h)
+    sl = slice(0, m)
+    return _pack(nh[sl], n_euv, n_fuv, np.ones(m), y_h2[sl], y_e[sl], tg[sl], tg[sl].copy()), \
+        10.0 * KYR
