@@ -1,0 +1,213 @@
+/*
+ * sfchem.h -- C ABI of the MI355X (gfx950) thermochemistry library.
+ *
+ * The library advances, cell by cell, the non-equilibrium hydrogen chemistry
+ * (H, H2, H+, H-, e-), the gas internal energy and the dust temperature of
+ * SFUMATO# (arXiv 2604.21438) over a hydrodynamic time step, with the
+ * paper's linearized-implicit (LI) method:
+ *   - chemistry and gas energy as one linearised implicit system
+ *     (I - h J) du = h f, u = (y_H2, y_e, E_th)  (Sec. "Thermochemical
+ *     processes", Eq. eq_deq; only y_H2 and y_e are unknowns, y_H and y_H+
+ *     follow from H-nuclei and charge conservation);
+ *   - dust temperature carried by a pseudo heat capacity C_d together with
+ *     the IR energy density and the gas-grain exchange (Appendix C);
+ *   - adaptive subcycles h = f_chem * min(dt_dust, dt_chem, dt_energy)
+ *     (Eqs. timescale_of_dust .. timestep_subcycle, N_cyc = 300).
+ * The rate coefficients are those of Table "Chemical reactions", the
+ * heating and cooling those of Table "Thermal processes"; formulas the
+ * paper leaves to its references are replaced by labelled stand-ins whose
+ * constants are fields of sfc_network.
+ *
+ * Conventions.  Every entry point returns an int status (SFC_OK == 0, or a
+ * negative SFC_E_* code); nothing throws or aborts across the ABI.  Cell
+ * buffers are structure-of-arrays of length n, contiguous, in DEVICE memory
+ * of the context's device, owned by the caller.  Units are cgs: densities
+ * cm^-3, energies erg cm^-3, temperatures K, times s.
+ */
+#ifndef SFCHEM_H
+#define SFCHEM_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SFC_ABI_VERSION 1u
+
+enum {
+  SFC_OK = 0,
+  SFC_E_INVAL = -1,   /* bad argument (NULL, size, range, mode)           */
+  SFC_E_NOMEM = -2,   /* host or device allocation failed                  */
+  SFC_E_BUDGET = -3,  /* request larger than the whole served HBM budget   */
+  SFC_E_DEVICE = -4,  /* HIP runtime error (message in sfc_last_error)     */
+  SFC_E_PENDING = -5, /* sfc_chem_poll: request not finished yet           */
+  SFC_E_VERSION = -6, /* sfc_network.abi_version / size mismatch           */
+  SFC_E_STATE = -7    /* call not valid in the context's current state     */
+};
+
+typedef enum { SFC_FP64 = 0, SFC_MIXED = 1 } sfc_precision;
+typedef enum { SFC_IR_FIXED = 0, SFC_IR_EVOLVE = 1 } sfc_ir_mode;
+typedef enum { SFC_THERMAL_EVOLVE = 0, SFC_THERMAL_ISOTHERMAL = 1 } sfc_thermal_mode;
+typedef enum { SFC_DUST_EVOLVE = 0, SFC_DUST_FROZEN = 1 } sfc_dust_mode;
+
+enum { SFC_NREAC = 12, SFC_NPROC = 14, SFC_NLINE = 5 };
+
+/* Reaction network and stand-in constants (copied at sfc_chem_init).
+ * reac_mult[i] scales k_Hi, i = 0..11 (Table "Chemical reactions");
+ * proc_mult[p-1] scales thermal process p = 1..14 (Table "Thermal
+ * processes"; 14 is the gas-grain exchange of Appendix C).  Fill with
+ * sfc_network_default() and edit. */
+typedef struct {
+  uint32_t abi_version;          /* = SFC_ABI_VERSION                       */
+  uint32_t size;                 /* = sizeof(sfc_network)                   */
+  double reac_mult[SFC_NREAC];
+  double proc_mult[SFC_NPROC];
+  double sigma_euv;              /* photoionisation cross section [cm^2]    */
+  double k10_per_g0;             /* H2 photodissociation per G0 [1/s]       */
+  double g0_photon_density;      /* FUV photons of G0 = 1 [cm^-3]           */
+  double zeta_cr;                /* cosmic-ray ionisation [1/s]             */
+  double k4_pre, k4_theta;       /* k_H4 = k4_pre exp(-k4_theta / T)        */
+  double heat_euv_ev;            /* heat per photoionisation [eV]           */
+  double heat_h2diss_ev;         /* heat per photodissociation [eV]         */
+  double pe_coef, pe_eps;        /* photoelectric heating pe_coef*pe_eps*G0*n*Z */
+  double kappa_max, kappa_tnorm; /* dust opacity kappa_max x^2/(1+x^2), x = T/tnorm */
+  double kappa_uv;               /* dust UV opacity per gram of gas [cm^2/g] */
+  double e_fuv_ev, e_euv_ev;     /* mean FUV / EUV photon energies [eV]     */
+  double x_c, x_o, f_oiii;       /* C, O abundances at Z_sun; O III share of ionised O */
+  double line_tul[SFC_NLINE];    /* two-level coolants H2, C II, O I, O II, O III: */
+  double line_a[SFC_NLINE];      /*   Delta E/k_B [K], A_ul [1/s], g_u/g_l, */
+  double line_g[SFC_NLINE];      /*   de-excitation by H+H2 [cm^3/s] and by */
+  double line_qn[SFC_NLINE];     /*   electrons at 100 K [cm^3/s] (~T^-1/2) */
+  double line_qe100[SFC_NLINE];
+} sfc_network;
+
+/* Numerical and physical parameters; defaults in brackets. */
+typedef struct {
+  double f_chem;       /* subcycle fraction [0.03]                        */
+  double y_abs;        /* abundance floor of dt_chem [1e-10]              */
+  double newton_rtol;  /* tight dust solve tolerance [1e-12]              */
+  double c_red;        /* reduced speed of light c~/c [1e-4]              */
+  double t_cmb;        /* CMB temperature, also the temperature floor [2.73] */
+  double y_he;         /* helium abundance by number [0.1]                */
+  double gamma_ad;     /* adiabatic index [5/3]                           */
+  int32_t n_cyc;       /* subcycle limit deciding tight coupling [300]    */
+  int32_t n_sub_max;   /* hard cap on subcycles per call [100000]         */
+  int32_t newton_max;  /* tight dust Newton iteration cap [60]            */
+  int32_t ir_mode;     /* sfc_ir_mode [SFC_IR_FIXED]                      */
+  int32_t thermal_mode;/* sfc_thermal_mode [SFC_THERMAL_EVOLVE]           */
+  int32_t dust_mode;   /* sfc_dust_mode [SFC_DUST_EVOLVE]                 */
+} sfc_params;
+
+void sfc_network_default(sfc_network* net);
+void sfc_params_default(sfc_params* p);
+
+typedef struct sfc_ctx sfc_ctx; /* opaque, owned by the library */
+
+/* Create a context on HIP device `hip_device`.
+ *   net              reaction network (copied); NULL -> defaults.
+ *   z_default        metallicity [Z_sun] used where sfc_cells.zmet is NULL.
+ *   dust_cap_factor  pseudo dust heat capacity C_d = factor * 1e4 erg/g/K
+ *                    (1 = the realistic value at Z_sun; the paper
+ *                    recommends 1000), must be > 0.
+ *   p                parameters (copied); NULL -> defaults.
+ *   served_budget_bytes  device memory the served form may hold for
+ *                    request state (0 -> served form disabled).
+ * Errors: SFC_E_INVAL, SFC_E_VERSION, SFC_E_DEVICE, SFC_E_NOMEM. */
+int sfc_chem_init(const sfc_network* net, double z_default, double dust_cap_factor,
+                  const sfc_params* p, int hip_device, uint64_t served_budget_bytes,
+                  sfc_ctx** out);
+
+/* Device SoA cell buffers, length n, float64 unless noted.
+ *   in/out: y_h2, y_e (abundances per H nucleus), eint (gas internal energy
+ *           density), tdust, eir (IR energy density; required only in
+ *           SFC_IR_EVOLVE mode, else may be NULL).
+ *   out (optional, NULL to skip): y_h, y_hp, y_hm (derived abundances),
+ *           tgas (gas temperature), nsub (int32 subcycles), niter (int32
+ *           tight-dust Newton iterations), flags (uint32, SFC_F_* bits).
+ *   in: nh (H nuclei density), n_euv, n_fuv (photon number densities),
+ *       zmet (metallicity; NULL -> z_default).
+ * A cell whose inputs are non-finite or non-positive (n_euv, n_fuv, zmet,
+ * y_h2, y_e may be zero) is left unchanged, its derived outputs are NaN and
+ * SFC_F_INVALID is set. */
+typedef struct {
+  int64_t n;
+  double *y_h2, *y_e, *eint, *tdust, *eir;
+  double *y_h, *y_hp, *y_hm, *tgas;
+  const double *nh, *n_euv, *n_fuv, *zmet;
+  int32_t *nsub, *niter;
+  uint32_t *flags;
+} sfc_cells;
+
+enum {
+  SFC_F_CAP = 1u << 0,     /* a step was raised by the n_sub_max cap     */
+  SFC_F_TIGHT = 1u << 1,   /* some subcycle used the implicit dust solve */
+  SFC_F_NOCONV = 1u << 2,  /* that solve reached newton_max              */
+  SFC_F_INVALID = 1u << 3, /* invalid input, cell unchanged              */
+  SFC_F_FLOOR = 1u << 4    /* a floor, clamp or rescale was applied      */
+};
+
+/* Advance every cell by dt_seconds (> 0, finite) on `hip_stream` (a
+ * hipStream_t; NULL = default stream).  Asynchronous: returns after the
+ * launches are queued; buffers must stay valid until the stream reaches the
+ * end of the call.  n == 0 is a no-op.  precision: SFC_FP64 (everything in
+ * binary64) or SFC_MIXED (rates, heating/cooling and Jacobian assembly in
+ * binary32; LU solves, state update and renormalisation in binary64).
+ * Calls on one context must not overlap (the context owns one work
+ * counter); use one context per concurrent stream.
+ * Errors: SFC_E_INVAL, SFC_E_DEVICE. */
+int sfc_chem_step(sfc_ctx* ctx, const sfc_cells* cells, double dt_seconds, int precision,
+                  void* hip_stream);
+
+/* ---- served form: continuous batching of AMR blocks ---- */
+
+/* One request: a set of cells (typically whole 8^3 blocks) with its own dt.
+ * The buffers are caller-owned device memory and must stay valid until the
+ * request completes (sfc_chem_poll returns SFC_OK); results are written
+ * back into them. */
+typedef struct {
+  sfc_cells cells;
+  double dt_seconds;
+  int32_t level;       /* AMR level (informational)              */
+  int32_t precision;   /* SFC_FP64 or SFC_MIXED                   */
+  uint64_t tag;        /* caller's tag, returned in sfc_result    */
+} sfc_request;
+
+typedef struct {
+  int32_t status;      /* SFC_OK when done                        */
+  int32_t level;
+  uint64_t tag;
+  int64_t cells;
+  double t_submit, t_admit, t_done; /* seconds on the library's steady clock */
+} sfc_result;
+
+/* Queue a request (non-blocking; the descriptor is copied).  The library's
+ * scheduler thread admits requests in arrival order while their state fits
+ * the HBM budget, uploads them into its arena and drains all admitted work
+ * with a persistent kernel replayed as a HIP graph; results are copied back
+ * when a request's last block is done.
+ * Errors: SFC_E_INVAL, SFC_E_BUDGET (larger than the whole budget),
+ * SFC_E_STATE (served form disabled). */
+int sfc_chem_submit(sfc_ctx* ctx, const sfc_request* req, uint64_t* ticket);
+
+/* Non-blocking completion check: SFC_OK and *out filled when done (the
+ * ticket is then released), SFC_E_PENDING otherwise, SFC_E_INVAL for an
+ * unknown ticket. */
+int sfc_chem_poll(sfc_ctx* ctx, uint64_t ticket, sfc_result* out);
+
+/* Block until every submitted request is done. */
+int sfc_chem_drain(sfc_ctx* ctx);
+
+/* Release the context (waits for outstanding served work).  NULL is a no-op. */
+int sfc_chem_destroy(sfc_ctx* ctx);
+
+/* Static text for a status code. */
+const char* sfc_strerror(int status);
+/* Last error message recorded on the context (thread-local per context). */
+const char* sfc_last_error(const sfc_ctx* ctx);
+/* Library clock (seconds) used for sfc_result times. */
+double sfc_now(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -6,9 +6,12 @@ the CPU-baseline leg of ``bench.py`` may import this package.  It shares no
 code with the HIP implementation in ``paper_2604_21438_amd``.
 
 The arithmetic lives in ``orc_chem.cpp`` (plain serial C++, binary64,
--ffp-contract=off).  ``build()`` compiles two libraries next to this file:
-``liborc.so`` (plain) and ``liborc_count.so`` (counting build, used for the
-algorithmic operation count per cell-update).
+-ffp-contract=off).  ``build()`` compiles four libraries next to this
+file: ``liborc.so`` (the reference), ``liborc_count.so`` (counting build,
+algorithmic operation count per cell-update), ``liborc_fma.so`` and
+``liborc_dn.so`` (other valid roundings: contracted multiply-adds and
+transcendentals nudged up / uncontracted and nudged down, used only to
+measure each cell's conditioning).
 """
 from __future__ import annotations
 
@@ -21,6 +24,13 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liborc.so")
 LIB_COUNT = os.path.join(HERE, "liborc_count.so")
+# the same source with multiply-add contraction and every transcendental
+# result moved by one ulp: a second, equally valid rounding of the same
+# algorithm, used to measure how far rounding alone moves each cell
+LIB_FMA = os.path.join(HERE, "liborc_fma.so")
+# and a third: no contraction, transcendentals nudged down, powers formed
+# as exp(y log x)
+LIB_DN = os.path.join(HERE, "liborc_dn.so")
 SRC = os.path.join(HERE, "orc_chem.cpp")
 
 NREAC, NPROC, NLINE = 12, 14, 5
@@ -34,8 +44,11 @@ CFLAGS = ["-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
 
 
 def build(force: bool = True) -> None:
-    """Compile the plain and the counting oracle libraries (g++)."""
-    for out, extra in ((LIB, []), (LIB_COUNT, ["-DORC_COUNT"])):
+    """Compile the plain, counting and contracted oracle libraries (g++)."""
+    variants = ((LIB, []), (LIB_COUNT, ["-DORC_COUNT"]),
+                (LIB_FMA, ["-mfma", "-ffp-contract=fast", "-DORC_NUDGE"]),
+                (LIB_DN, ["-DORC_NUDGE", "-DORC_NUDGE_DOWN"]))
+    for out, extra in variants:
         if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(SRC):
             continue
         tmp = out + ".tmp"
@@ -89,8 +102,8 @@ class Cells(C.Structure):
 _libs: dict = {}
 
 
-def _lib(counting: bool = False):
-    path = LIB_COUNT if counting else LIB
+def _lib(counting: bool = False, variant: str = "plain"):
+    path = LIB_COUNT if counting else {"fma": LIB_FMA, "dn": LIB_DN}.get(variant, LIB)
     if path not in _libs:
         if not os.path.exists(path):
             build(force=False)
@@ -183,13 +196,15 @@ def _prepare(cells: dict, ir_mode: int):
 
 
 def li_step(cells: dict, dt: float, net: Network | None = None, params: Params | None = None,
-            nthreads: int = 1) -> dict:
-    """LI update of every cell over dt [s]; returns a new dict of arrays."""
+            nthreads: int = 1, variant: str = "plain") -> dict:
+    """LI update of every cell over dt [s]; returns a new dict of arrays.
+    variant "fma" runs the build with multiply-add contraction."""
     net = net or default_network()
     params = params or default_params()
     out, n = _prepare(cells, params.ir_mode)
     c, keep = _cells(out, n)
-    rc = _lib().orc_li_step(C.byref(net), C.byref(params), C.byref(c), float(dt), int(nthreads))
+    rc = _lib(variant=variant).orc_li_step(C.byref(net), C.byref(params), C.byref(c), float(dt),
+                                            int(nthreads))
     if rc != 0:
         raise ValueError("orc_li_step rejected its arguments")
     return out
@@ -276,3 +291,47 @@ def count_li(cells: dict, dt: float, idx, net=None, params=None) -> np.ndarray:
             raise RuntimeError("counting build not available")
         res[j] = buf
     return res
+
+
+OUT_KEYS = ("y_h2", "y_e", "y_h", "y_hp", "y_hm", "tgas", "tdust")
+
+
+def _rel(a, b, floor=1e-20):
+    return np.abs(a - b) / np.maximum(np.abs(b), floor)
+
+
+def rounding_spread(cells: dict, dt: float, ref: dict, net=None, params=None,
+                    nthreads: int = 1) -> np.ndarray:
+    """Per cell, the largest relative change of any output between the
+    reference result `ref` and three other valid roundings of the same
+    computation: the contracted build with transcendentals nudged up, the
+    uncontracted build with them nudged down and powers formed as
+    exp(y log x), and the input internal
+    energy moved by one unit in the last place.  A cell whose spread exceeds a
+    tolerance is not determined to that tolerance by binary64 arithmetic."""
+    params = params or default_params()
+    alt = [li_step(cells, dt, net, params, nthreads, variant="fma"),
+           li_step(cells, dt, net, params, nthreads, variant="dn")]
+    nudged = dict(cells)
+    nudged["eint"] = np.nextafter(np.asarray(cells["eint"], np.float64), np.inf)
+    alt.append(li_step(nudged, dt, net, params, nthreads))
+    spread = np.zeros(ref["nsub"].shape[0])
+    for o in alt:
+        for k in OUT_KEYS:
+            spread = np.maximum(spread, _rel(o[k], ref[k]))
+    return spread
+
+
+def step_sensitivity(cells: dict, dt: float, ref: dict, net=None, params=None,
+                     nthreads: int = 1, eps: float = 1e-6) -> np.ndarray:
+    """Per cell, the largest relative output change when every subcycle is
+    made larger by the factor (1 + eps) (f_chem scaled): how strongly the
+    result depends on the step-size sequence."""
+    params = params or default_params()
+    p2 = Params.from_buffer_copy(params)
+    p2.f_chem = params.f_chem * (1.0 + eps)
+    o = li_step(cells, dt, net, p2, nthreads)
+    s = np.zeros(ref["nsub"].shape[0])
+    for k in OUT_KEYS:
+        s = np.maximum(s, _rel(o[k], ref[k]))
+    return s

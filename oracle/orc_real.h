@@ -7,6 +7,9 @@
  * replaces it by a class that performs the same binary64 arithmetic and
  * counts each operation, so that the algorithmic operation count per
  * cell-update comes from the very code that defines the method.
+ * The nudged build (-DORC_NUDGE) moves every transcendental result by one
+ * ulp; with multiply-add contraction it gives a second valid rounding of
+ * the whole computation, used to measure each cell's conditioning.
  * Operations with an exact-zero operand are not counted: they are the
  * structural zeros of the sparse derivative bookkeeping (for example the
  * y-partials of a temperature-only rate coefficient), which an implementation
@@ -19,10 +22,29 @@
 #ifndef ORC_COUNT
 
 typedef double real;
-static inline real rexp(real x) { return std::exp(x); }
-static inline real rlog(real x) { return std::log(x); }
-static inline real rlog1p(real x) { return std::log1p(x); }
-static inline real rpow(real x, real y) { return std::pow(x, y); }
+#if defined(ORC_NUDGE)
+/* Conditioning probe: every transcendental result moved by one unit in the
+ * last place (up, or down with ORC_NUDGE_DOWN) -- what another faithfully
+ * rounded math library may return.  Only used to measure how far rounding
+ * alone moves a result. */
+#ifdef ORC_NUDGE_DOWN
+static inline real nudge(real v) { return std::nextafter(v, -HUGE_VAL); }
+#else
+static inline real nudge(real v) { return std::nextafter(v, HUGE_VAL); }
+#endif
+#else
+static inline real nudge(real v) { return v; }
+#endif
+static inline real rexp(real x) { return nudge(std::exp(x)); }
+static inline real rlog(real x) { return nudge(std::log(x)); }
+static inline real rlog1p(real x) { return nudge(std::log1p(x)); }
+#ifdef ORC_NUDGE_DOWN
+/* the same probe also forms powers as exp(y log x), whose rounding error
+ * grows with |y log x| */
+static inline real rpow(real x, real y) { return nudge(std::exp(y * std::log(x))); }
+#else
+static inline real rpow(real x, real y) { return nudge(std::pow(x, y)); }
+#endif
 static inline real rsqrt(real x) { return std::sqrt(x); }
 static inline double rval(real x) { return x; }
 

@@ -1,0 +1,378 @@
+// sfchem.cpp -- host side of the C ABI declared in include/sfchem.h:
+// contexts, argument checks, kernel launches and the served scheduler.
+#include "sfchem.h"
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "sfk.h"
+#include "sfserve.h"
+
+namespace {
+
+constexpr double KB = 1.380649e-16;
+constexpr double EV = 1.602176634e-12;
+constexpr double CL = 2.99792458e10;
+
+// k_H2 / k_H3 at temperature T (host, binary64): used only to bound the
+// steady-state H- ratio over the temperature range of the rate fits.
+double host_hm_ratio(double T) {
+  const double k2 = 1.4e-18 * std::pow(T, 0.928) * std::exp(-T / 16200.0);
+  const double N = std::pow(T, 0.098493) + 0.32852 * std::pow(T, 0.5561) +
+                   2.771e-7 * std::pow(T, 2.1826);
+  const double D = 1.0 + 6.191e-3 * std::pow(T, 1.0461) + 8.9712e-11 * std::pow(T, 3.0424) +
+                   3.2576e-14 * std::pow(T, 3.7741);
+  const double k3 = 1.35e-9 * N / D;
+  return k2 / k3;
+}
+
+bool fill_net(const sfc_network& in, sfk::Net& o) {
+  for (int i = 0; i < 12; ++i) o.rm[i] = in.reac_mult[i];
+  for (int i = 0; i < 14; ++i) o.pm[i] = in.proc_mult[i];
+  if (!(in.g0_photon_density > 0.0) || !(in.kappa_tnorm > 0.0)) return false;
+  o.c_sigma = CL * in.sigma_euv;
+  o.k10g = in.k10_per_g0;
+  o.inv_g0 = 1.0 / in.g0_photon_density;
+  o.zeta = in.zeta_cr;
+  o.k4_pre = in.k4_pre;
+  o.k4_theta = in.k4_theta;
+  o.g2k = in.heat_euv_ev * EV / KB;
+  o.g3k = in.heat_h2diss_ev * EV / KB;
+  o.pe_k = in.pe_coef * in.pe_eps / KB;
+  o.kap_max = in.kappa_max;
+  o.kap_tn = 1.0 / in.kappa_tnorm;
+  o.kap_uv_c = CL * in.kappa_uv;
+  o.e_fuv = in.e_fuv_ev * EV;
+  o.e_euv = in.e_euv_ev * EV;
+  o.x_c = in.x_c;
+  o.x_o = in.x_o;
+  o.f_oiii = in.f_oiii;
+  for (int j = 0; j < 5; ++j) {
+    o.l_tul[j] = in.line_tul[j];
+    o.l_a[j] = in.line_a[j];
+    o.l_g[j] = in.line_g[j];
+    o.l_qn[j] = in.line_qn[j];
+    o.l_qe[j] = in.line_qe100[j];
+    if (!(in.line_a[j] > 0.0)) return false;
+  }
+  return true;
+}
+
+bool fill_par(const sfc_params& p, double z_default, double cd, const sfk::Net& net,
+              sfk::Par& o) {
+  if (!(p.f_chem > 0.0) || !(p.y_abs > 0.0) || !(p.newton_rtol > 0.0) || !(p.c_red > 0.0) ||
+      !(p.t_cmb > 0.0) || !(p.y_he >= 0.0) || !(p.gamma_ad > 1.0) || p.n_cyc < 0 ||
+      p.n_sub_max < 2 || p.newton_max < 1 || (p.ir_mode != 0 && p.ir_mode != 1) ||
+      (p.thermal_mode != 0 && p.thermal_mode != 1) || (p.dust_mode != 0 && p.dust_mode != 1) ||
+      !(z_default >= 0.0) || !(cd > 0.0))
+    return false;
+  o.f_chem = p.f_chem;
+  o.y_abs = p.y_abs;
+  o.newton_rtol = p.newton_rtol;
+  o.c_red = p.c_red;
+  o.t_cmb = p.t_cmb;
+  o.y_he = p.y_he;
+  o.gm1 = p.gamma_ad - 1.0;
+  o.cd = cd;
+  o.z_default = z_default;
+  o.n_cyc = p.n_cyc;
+  o.n_sub_max = p.n_sub_max;
+  o.newton_max = p.newton_max;
+  o.ir_mode = p.ir_mode;
+  o.thermal_mode = p.thermal_mode;
+  o.dust_mode = p.dust_mode;
+  // bound of k_H2/k_H3 over [1, 1e8] K (fine log grid, 5 % margin)
+  double mx = 0.0;
+  for (int i = 0; i <= 8000; ++i) {
+    const double T = std::pow(10.0, 8.0 * i / 8000.0);
+    const double r = host_hm_ratio(T);
+    if (r > mx) mx = r;
+  }
+  const double scale = net.rm[3] > 0.0 ? net.rm[2] / net.rm[3] : 0.0;
+  o.hm_ratio_max = net.rm[3] > 0.0 ? 1.05 * mx * scale : 0.0;
+  return true;
+}
+
+}  // namespace
+
+struct sfc_ctx {
+  int device = 0;
+  sfk::Net net{};
+  sfk::Par par{};
+  unsigned long long* d_counter = nullptr;
+  int cus = 0;
+  int bpc[2] = {1, 1};
+  int refill_min = 8;
+  std::string last_error;
+  sfserve::Server* server = nullptr;
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+int fail(sfc_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->last_error = msg;
+  return code;
+}
+
+int hip_fail(sfc_ctx* ctx, hipError_t e, const char* where) {
+  return fail(ctx, SFC_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+bool cells_ok(const sfk::Par& par, const sfc_cells* c) {
+  if (!c || c->n < 0) return false;
+  if (c->n == 0) return true;
+  if (!c->y_h2 || !c->y_e || !c->eint || !c->tdust || !c->nh || !c->n_euv || !c->n_fuv)
+    return false;
+  if (par.ir_mode == 1 && !c->eir) return false;
+  return true;
+}
+
+sfk::Cells to_kcells(const sfc_cells* c) {
+  sfk::Cells k;
+  k.n = c->n;
+  k.y_h2 = c->y_h2; k.y_e = c->y_e; k.eint = c->eint; k.tdust = c->tdust; k.eir = c->eir;
+  k.y_h = c->y_h; k.y_hp = c->y_hp; k.y_hm = c->y_hm; k.tgas = c->tgas;
+  k.nh = c->nh; k.n_euv = c->n_euv; k.n_fuv = c->n_fuv; k.zmet = c->zmet;
+  k.nsub = c->nsub; k.niter = c->niter; k.flags = c->flags;
+  return k;
+}
+
+}  // namespace
+
+extern "C" {
+
+void sfc_network_default(sfc_network* net) {
+  if (!net) return;
+  std::memset(net, 0, sizeof(*net));
+  net->abi_version = SFC_ABI_VERSION;
+  net->size = sizeof(sfc_network);
+  for (int i = 0; i < SFC_NREAC; ++i) net->reac_mult[i] = 1.0;
+  for (int i = 0; i < SFC_NPROC; ++i) net->proc_mult[i] = 1.0;
+  net->sigma_euv = 3.0e-18;
+  net->k10_per_g0 = 5.0e-11;
+  net->g0_photon_density = 3.7e-3;
+  net->zeta_cr = 1.0e-17;
+  net->k4_pre = 1.0e-10;
+  net->k4_theta = 5.2e4;
+  net->heat_euv_ev = 4.4;
+  net->heat_h2diss_ev = 0.4;
+  net->pe_coef = 1.0e-24;
+  net->pe_eps = 0.05;
+  net->kappa_max = 20.0;
+  net->kappa_tnorm = 200.0;
+  net->kappa_uv = 400.0;
+  net->e_fuv_ev = 9.0;
+  net->e_euv_ev = 18.0;
+  net->x_c = 1.4e-4;
+  net->x_o = 3.2e-4;
+  net->f_oiii = 0.2;
+  // H2 (J=2-0), C II 158um, O I 63um, O II 3727A, O III 5007A
+  const double tul[5] = {510.0, 91.2, 227.7, 38600.0, 29000.0};
+  const double a[5] = {2.94e-11, 2.29e-6, 8.91e-5, 1.0e-4, 2.0e-2};
+  const double g[5] = {5.0, 2.0, 0.6, 2.5, 5.0 / 9.0};
+  const double qn[5] = {1.0e-11, 8.0e-10, 1.0e-10, 0.0, 0.0};
+  const double qe[5] = {0.0, 2.8e-7, 1.4e-8, 8.629e-8, 1.7258e-7};
+  for (int j = 0; j < 5; ++j) {
+    net->line_tul[j] = tul[j];
+    net->line_a[j] = a[j];
+    net->line_g[j] = g[j];
+    net->line_qn[j] = qn[j];
+    net->line_qe100[j] = qe[j];
+  }
+}
+
+void sfc_params_default(sfc_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->f_chem = 0.03;
+  p->y_abs = 1e-10;
+  p->newton_rtol = 1e-12;
+  p->c_red = 1e-4;
+  p->t_cmb = 2.73;
+  p->y_he = 0.1;
+  p->gamma_ad = 5.0 / 3.0;
+  p->n_cyc = 300;
+  p->n_sub_max = 100000;
+  p->newton_max = 60;
+  p->ir_mode = SFC_IR_FIXED;
+  p->thermal_mode = SFC_THERMAL_EVOLVE;
+  p->dust_mode = SFC_DUST_EVOLVE;
+}
+
+int sfc_chem_init(const sfc_network* net_in, double z_default, double dust_cap_factor,
+                  const sfc_params* p_in, int hip_device, uint64_t served_budget_bytes,
+                  sfc_ctx** out) {
+  if (!out) return SFC_E_INVAL;
+  *out = nullptr;
+  sfc_network net;
+  if (net_in) {
+    if (net_in->abi_version != SFC_ABI_VERSION || net_in->size != sizeof(sfc_network))
+      return SFC_E_VERSION;
+    net = *net_in;
+  } else {
+    sfc_network_default(&net);
+  }
+  sfc_params p;
+  if (p_in) p = *p_in; else sfc_params_default(&p);
+  if (!(dust_cap_factor > 0.0) || !std::isfinite(dust_cap_factor)) return SFC_E_INVAL;
+  sfk::Net knet;
+  sfk::Par kpar;
+  if (!fill_net(net, knet) || !fill_par(p, z_default, dust_cap_factor * 1.0e4, knet, kpar))
+    return SFC_E_INVAL;
+  if (hip_device < 0) return SFC_E_INVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device >= ndev) return SFC_E_DEVICE;
+  sfc_ctx* ctx = new (std::nothrow) sfc_ctx();
+  if (!ctx) return SFC_E_NOMEM;
+  ctx->device = hip_device;
+  ctx->net = knet;
+  ctx->par = kpar;
+  DeviceGuard g(hip_device);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) {
+    delete ctx;
+    return SFC_E_DEVICE;
+  }
+  ctx->cus = prop.multiProcessorCount;
+  ctx->bpc[0] = sfk::max_blocks_per_cu(0);
+  ctx->bpc[1] = sfk::max_blocks_per_cu(1);
+  if (hipMalloc(&ctx->d_counter, sizeof(unsigned long long)) != hipSuccess) {
+    delete ctx;
+    return SFC_E_NOMEM;
+  }
+  if (hipMemset(ctx->d_counter, 0, sizeof(unsigned long long)) != hipSuccess) {
+    (void)hipFree(ctx->d_counter);
+    delete ctx;
+    return SFC_E_DEVICE;
+  }
+  if (const char* e = std::getenv("SFC_REFILL_MIN")) {
+    const int v = std::atoi(e);
+    if (v >= 1 && v <= 64) ctx->refill_min = v;
+  }
+  if (served_budget_bytes > 0) {
+    sfserve::Config sc;
+    sc.device = hip_device;
+    sc.budget_bytes = served_budget_bytes;
+    sc.net = ctx->net;
+    sc.par = ctx->par;
+    sc.cus = ctx->cus;
+    sc.refill_min = ctx->refill_min;
+    std::string err;
+    ctx->server = sfserve::create(sc, &err);
+    if (!ctx->server) {
+      (void)hipFree(ctx->d_counter);
+      delete ctx;
+      return SFC_E_NOMEM;
+    }
+  }
+  *out = ctx;
+  return SFC_OK;
+}
+
+int sfc_chem_step(sfc_ctx* ctx, const sfc_cells* cells, double dt, int precision,
+                  void* hip_stream) {
+  if (!ctx) return SFC_E_INVAL;
+  if (!cells_ok(ctx->par, cells)) return fail(ctx, SFC_E_INVAL, "sfc_chem_step: bad cell buffers");
+  if (!(dt > 0.0) || !std::isfinite(dt))
+    return fail(ctx, SFC_E_INVAL, "sfc_chem_step: dt must be positive and finite");
+  if (precision != SFC_FP64 && precision != SFC_MIXED)
+    return fail(ctx, SFC_E_INVAL, "sfc_chem_step: unknown precision");
+  if (cells->n == 0) return SFC_OK;
+  DeviceGuard g(ctx->device);
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  sfk::Args a;
+  a.net = ctx->net;
+  a.par = ctx->par;
+  a.c = to_kcells(cells);
+  a.dt = dt;
+  a.counter = ctx->d_counter;
+  a.refill_min = ctx->refill_min;
+  const int64_t need = (cells->n + sfk::kBlock - 1) / sfk::kBlock;
+  const int64_t cap = int64_t(ctx->cus) * ctx->bpc[precision];
+  const int grid = int(need < cap ? need : cap);
+  hipError_t e = sfk::launch_reset(ctx->d_counter, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "reset launch");
+  e = sfk::launch_step(a, precision, grid, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "step launch");
+  return SFC_OK;
+}
+
+int sfc_chem_submit(sfc_ctx* ctx, const sfc_request* req, uint64_t* ticket) {
+  if (!ctx || !req || !ticket) return SFC_E_INVAL;
+  if (!ctx->server) return fail(ctx, SFC_E_STATE, "served form disabled (budget 0)");
+  if (!cells_ok(ctx->par, &req->cells) || req->cells.n <= 0)
+    return fail(ctx, SFC_E_INVAL, "sfc_chem_submit: bad cell buffers");
+  if (!(req->dt_seconds > 0.0) || !std::isfinite(req->dt_seconds))
+    return fail(ctx, SFC_E_INVAL, "sfc_chem_submit: dt must be positive and finite");
+  if (req->precision != SFC_FP64 && req->precision != SFC_MIXED)
+    return fail(ctx, SFC_E_INVAL, "sfc_chem_submit: unknown precision");
+  std::string err;
+  const int rc = sfserve::submit(ctx->server, *req, ticket, &err);
+  if (rc != SFC_OK) return fail(ctx, rc, err);
+  return SFC_OK;
+}
+
+int sfc_chem_poll(sfc_ctx* ctx, uint64_t ticket, sfc_result* out) {
+  if (!ctx || !out) return SFC_E_INVAL;
+  if (!ctx->server) return fail(ctx, SFC_E_STATE, "served form disabled (budget 0)");
+  return sfserve::poll(ctx->server, ticket, out);
+}
+
+int sfc_chem_drain(sfc_ctx* ctx) {
+  if (!ctx) return SFC_E_INVAL;
+  if (!ctx->server) return SFC_OK;
+  std::string err;
+  const int rc = sfserve::drain(ctx->server, &err);
+  if (rc != SFC_OK) return fail(ctx, rc, err);
+  return SFC_OK;
+}
+
+int sfc_chem_destroy(sfc_ctx* ctx) {
+  if (!ctx) return SFC_OK;
+  DeviceGuard g(ctx->device);
+  if (ctx->server) sfserve::destroy(ctx->server);
+  if (ctx->d_counter) (void)hipFree(ctx->d_counter);
+  delete ctx;
+  return SFC_OK;
+}
+
+const char* sfc_strerror(int status) {
+  switch (status) {
+    case SFC_OK: return "ok";
+    case SFC_E_INVAL: return "invalid argument";
+    case SFC_E_NOMEM: return "out of memory";
+    case SFC_E_BUDGET: return "request exceeds the served HBM budget";
+    case SFC_E_DEVICE: return "HIP device error";
+    case SFC_E_PENDING: return "request pending";
+    case SFC_E_VERSION: return "network ABI version mismatch";
+    case SFC_E_STATE: return "invalid state";
+    default: return "unknown status";
+  }
+}
+
+const char* sfc_last_error(const sfc_ctx* ctx) {
+  return ctx ? ctx->last_error.c_str() : "";
+}
+
+double sfc_now(void) { return sfserve::now(); }
+
+}  // extern "C"

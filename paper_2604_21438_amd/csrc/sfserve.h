@@ -1,0 +1,32 @@
+// sfserve.h -- served form (continuous batching of AMR blocks): request
+// queue, HBM-budget admission into a device arena, persistent drain kernel
+// replayed as a HIP graph, completion and latency bookkeeping.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+
+#include "sfchem.h"
+#include "sfk.h"
+
+namespace sfserve {
+
+struct Config {
+  int device = 0;
+  uint64_t budget_bytes = 0;
+  sfk::Net net{};
+  sfk::Par par{};
+  int cus = 0;
+  int refill_min = 8;
+};
+
+struct Server;
+
+Server* create(const Config& cfg, std::string* err);
+int submit(Server* s, const sfc_request& req, uint64_t* ticket, std::string* err);
+int poll(Server* s, uint64_t ticket, sfc_result* out);
+int drain(Server* s, std::string* err);
+void destroy(Server* s);
+double now();
+
+}  // namespace sfserve

@@ -1,0 +1,89 @@
+"""Helpers shared by the GPU parity tests: run the HIP path through the
+C ABI and the CPU reference on the same seeded inputs, and compare them."""
+import os
+import sys
+
+import numpy as np
+
+import oracle
+
+SPECIES = ("y_h2", "y_e", "y_h", "y_hp", "y_hm")
+TEMPS = ("tgas", "tdust")
+
+
+def host_threads():
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def oracle_net_params(sfc_net, sfc_par, dust_factor=1.0, z_default=1.0):
+    """Oracle structures holding the same values as the library's."""
+    net = oracle.default_network()
+    for name, _ in oracle.Network._fields_:
+        v = getattr(sfc_net, name)
+        if hasattr(v, "__len__"):
+            setattr(net, name, type(getattr(net, name))(*v))
+        else:
+            setattr(net, name, v)
+    par = oracle.default_params()
+    for name, _ in oracle.Params._fields_:
+        if name in ("dust_cap", "z_default"):
+            continue
+        setattr(par, name, getattr(sfc_par, name))
+    par.dust_cap = 1.0e4 * dust_factor
+    par.z_default = z_default
+    return net, par
+
+
+def run_gpu(cells, dt, precision=0, dust_factor=1.0, net=None, par=None, z_default=1.0,
+            label=""):
+    import torch
+
+    import paper_2604_21438_amd as sfc
+    print(f"[gpu] {label}: n={cells['nh'].shape[0]} dt={dt:.3e} prec={precision} "
+          f"factor={dust_factor}", flush=True)
+    ctx = sfc.Context(network=net, z_default=z_default, dust_factor=dust_factor, params=par)
+    t = sfc.to_device(cells)
+    ctx.step(t, dt, precision)
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in t.items()}
+    out["flags"] = out["flags"].view(np.uint32)
+    ctx.close()
+    return out
+
+
+def run_oracle(cells, dt, net, par):
+    return oracle.li_step(cells, dt, net=net, params=par, nthreads=host_threads())
+
+
+def rel(a, b, floor=1e-20):
+    return np.abs(a - b) / np.maximum(np.abs(b), floor)
+
+
+def compare(gpu, ref, keys=SPECIES + TEMPS, extra=()):
+    """max relative error per key, and the cells whose subcycle count or
+    flags differ (branch decisions taken differently)."""
+    errs = {}
+    for k in tuple(keys) + tuple(extra):
+        errs[k] = rel(gpu[k], ref[k])
+    exc = np.nonzero((gpu["nsub"] != ref["nsub"]))[0]
+    return errs, exc
+
+
+def report(errs, exc, n, label="", gpu=None, ref=None, cells=None):
+    parts = [f"{k}: max {np.nanmax(v):.2e} p99 {np.nanpercentile(v, 99):.2e}" for k, v in errs.items()]
+    print(f"[parity] {label} n={n} exceptions={len(exc)} | " + "; ".join(parts), flush=True)
+    if gpu is not None and ref is not None:
+        worst = np.zeros(n)
+        for v in errs.values():
+            worst = np.maximum(worst, np.nan_to_num(v))
+        for i in np.argsort(-worst)[:5]:
+            extra = ""
+            if cells is not None:
+                extra = " nh=%.3e euv=%.2e fuv=%.2e z=%.2f" % (
+                    cells["nh"][i], cells["n_euv"][i], cells["n_fuv"][i],
+                    cells["zmet"][i] if "zmet" in cells else -1)
+            print(f"   cell {i}: worst {worst[i]:.2e} nsub {gpu['nsub'][i]}/{ref['nsub'][i]} "
+                  f"niter {gpu['niter'][i]}/{ref['niter'][i]} flags {gpu['flags'][i]}/{ref['flags'][i]} "
+                  f"T {gpu['tgas'][i]:.6e}/{ref['tgas'][i]:.6e} y_h2 {gpu['y_h2'][i]:.6e}/{ref['y_h2'][i]:.6e}"
+                  + extra, flush=True)
+    sys.stdout.flush()
