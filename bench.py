@@ -65,6 +65,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-cells", type=int, default=8192)
     ap.add_argument("--cells", type=int, default=None, help="fewer cells (testing only)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run three device-to-device copies of MIB MiB (a kernel of "
+                         "known traffic, to scale the HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; the update has no cross-GPU "
@@ -72,6 +75,17 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] copied {args.calibrate_copy} MiB three times "
+            f"(each: {n * 8} bytes read, {n * 8} bytes written)")
+        return
 
     import paper_2604_21438_amd as sfc
     from paper_2604_21438_amd import workloads as W

@@ -109,7 +109,7 @@ struct sfc_ctx {
   unsigned long long* d_counter = nullptr;
   int cus = 0;
   int bpc[2] = {1, 1};
-  int refill_min = 8;
+  int refill_min = 1;
   std::string last_error;
   sfserve::Server* server = nullptr;
 };

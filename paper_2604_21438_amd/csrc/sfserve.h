@@ -17,7 +17,7 @@ struct Config {
   sfk::Net net{};
   sfk::Par par{};
   int cus = 0;
-  int refill_min = 8;
+  int refill_min = 1;
 };
 
 struct Server;
