@@ -55,6 +55,99 @@ def relerr(a, b, floor=1e-20):
                 median=float(np.nanmedian(e)))
 
 
+def pct(a, q):
+    return float(np.percentile(np.asarray(a, np.float64), q))
+
+
+def served_leg(args, sfc, W, torch):
+    """Requests of 8^3 blocks (count log-uniform in [1, max_blocks]) cut out
+    of the log-normal / point-source population, levels 0..5 with
+    dt = 10 kyr / 2^L, dust factor 100.  Legs: the plain path called
+    request by request (binary64, then mixed), the served form with every
+    request queued at once (its capacity), and the served form fed by a
+    Poisson process at a fraction of that capacity (latency = done - arrival)."""
+    reqs, _ = W.amr_requests(args.served_requests, max_blocks=args.served_max_blocks,
+                             side=args.served_side)
+    sizes = np.array([r["cells"]["nh"].shape[0] for r in reqs])
+    total = int(sizes.sum())
+    log(f"[bench] served workload: {len(reqs)} requests, {total} cells, "
+        f"blocks/request mean {sizes.mean() / 512:.1f} max {sizes.max() // 512}")
+    bufs = [sfc.to_device(r["cells"]) for r in reqs]
+    prist = [{k: b[k].clone() for k in STATE_KEYS} for b in bufs]
+
+    def restore():
+        for b, p in zip(bufs, prist):
+            for k in STATE_KEYS:
+                b[k].copy_(p[k])
+        torch.cuda.synchronize()
+
+    factor = 100.0
+    out = dict(workload=f"{len(reqs)} requests of 8^3 blocks, blocks/request log-uniform in "
+                        f"[1,{args.served_max_blocks}], levels 0..5 (dt = 10 kyr / 2^L), "
+                        f"cells from the {args.served_side}^3 log-normal + 8 point-source "
+                        f"population, dust factor 100",
+               requests=len(reqs), cells=total)
+    ctx = sfc.Context(dust_factor=factor, served_budget_bytes=args.served_budget_mib << 20)
+
+    def plain(prec, label):
+        restore()
+        t0 = time.perf_counter()
+        for b, r in zip(bufs, reqs):
+            ctx.step(b, r["dt"], prec)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        log(f"[bench] served/{label}: {el:.3f} s")
+        return el
+
+    def served(prec, arrivals, label):
+        restore()
+        tickets = []
+        t0 = sfc.now()
+        for i, (b, r) in enumerate(zip(bufs, reqs)):
+            if arrivals is not None:
+                while sfc.now() - t0 < arrivals[i]:
+                    time.sleep(50e-6)
+            tickets.append(ctx.submit(b, r["dt"], prec, level=r["level"], tag=i, sync=False))
+        ctx.drain()
+        res = [ctx.poll(t) for t in tickets]
+        t_first = min(x["t_submit"] for x in res)
+        t_last = max(x["t_done"] for x in res)
+        lat = np.array([x["t_done"] - x["t_submit"] for x in res])
+        qd = np.array([x["t_admit"] - x["t_submit"] for x in res])
+        log(f"[bench] served/{label}: makespan {t_last - t_first:.3f} s, latency p50 "
+            f"{np.median(lat) * 1e3:.1f} ms p99 {pct(lat, 99) * 1e3:.1f} ms")
+        return dict(value=total / (t_last - t_first), makespan_s=t_last - t_first,
+                    latency_ms=dict(p50=pct(lat, 50) * 1e3, p99=pct(lat, 99) * 1e3,
+                                    max=float(lat.max()) * 1e3),
+                    admission_wait_ms=dict(p50=pct(qd, 50) * 1e3, p99=pct(qd, 99) * 1e3))
+
+    def snapshot():
+        torch.cuda.synchronize()
+        return {k: torch.cat([b[k] for b in bufs]).cpu().numpy()
+                for k in ("y_h2", "y_e", "y_h", "y_hp", "y_hm", "tgas", "tdust")}
+
+    el = plain(sfc.FP64, "plain fp64")
+    out["plain_fp64"] = dict(value=total / el, seconds=el)
+    ref = snapshot()
+    el = plain(sfc.MIXED, "plain mixed")
+    out["plain_mixed"] = dict(value=total / el, seconds=el)
+    for prec, name in ((sfc.MIXED, "served_mixed"), (sfc.FP64, "served_fp64")):
+        cap = served(prec, None, f"{name} all queued")
+        got = snapshot()
+        leg = dict(all_queued=cap)
+        if prec == sfc.MIXED:
+            leg["vs_plain_fp64"] = {k: relerr(got[k], ref[k]) for k in got}
+        rate = args.served_load * cap["value"] / sizes.mean()
+        arr = W.poisson_arrivals(len(reqs), rate)
+        leg["poisson"] = dict(load=args.served_load, rate_req_per_s=rate,
+                              **served(prec, arr, f"{name} poisson load {args.served_load}"))
+        out[name] = leg
+    out["served_mixed_vs_plain_fp64_throughput"] = (out["served_mixed"]["all_queued"]["value"] /
+                                                    out["plain_fp64"]["value"])
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,6 +156,12 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=200)
+    ap.add_argument("--served-max-blocks", type=int, default=256)
+    ap.add_argument("--served-side", type=int, default=128)
+    ap.add_argument("--served-budget-mib", type=int, default=8192)
+    ap.add_argument("--served-load", type=float, default=0.8)
     ap.add_argument("--cpu-cells", type=int, default=8192)
     ap.add_argument("--cells", type=int, default=None, help="fewer cells (testing only)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -205,6 +304,10 @@ def main():
                                         for k in ("y_h2", "y_e", "y_h", "y_hp", "y_hm", "tgas",
                                                   "tdust")},
                                stats=describe(outmx))
+
+    # ---- served form: AMR-shaped requests with Poisson arrivals ----
+    if not args.no_served:
+        result["served"] = served_leg(args, sfc, W, torch)
 
     # ---- CPU reference on a sample of the same cells ----
     if not args.no_cpu:

@@ -234,7 +234,13 @@ class Context:
                     "sfc_chem_step")
 
     def submit(self, cells: dict, dt: float, precision: int = MIXED, level: int = 0,
-               tag: int = 0) -> int:
+               tag: int = 0, sync: bool = True) -> int:
+        """Queue a request; the tensors are updated in place once poll()
+        reports it done.  The library reads them on its own stream, so by
+        default torch's current stream is synchronised first."""
+        import torch
+        if sync:
+            torch.cuda.current_stream(self.device).synchronize()
         r = SfcRequest()
         r.cells = make_cells(cells)
         r.dt_seconds = float(dt)

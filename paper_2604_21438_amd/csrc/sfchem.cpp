@@ -277,11 +277,12 @@ int sfc_chem_init(const sfc_network* net_in, double z_default, double dust_cap_f
     sc.cus = ctx->cus;
     sc.refill_min = ctx->refill_min;
     std::string err;
-    ctx->server = sfserve::create(sc, &err);
+    int code = SFC_E_NOMEM;
+    ctx->server = sfserve::create(sc, &err, &code);
     if (!ctx->server) {
       (void)hipFree(ctx->d_counter);
       delete ctx;
-      return SFC_E_NOMEM;
+      return code;
     }
   }
   *out = ctx;

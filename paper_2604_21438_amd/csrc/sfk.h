@@ -55,31 +55,52 @@ struct Args {
   int32_t refill_min;           // refill a wave once this many lanes are idle
 };
 
-// Served form: one work item = a contiguous range of cells of one slot.
-struct Slot {
-  Cells c;          // arena-resident state of the request
-  double dt;
-  int32_t precision;
-  int32_t pad;
+// Served form.  Requests are published by the host into a ring that lives
+// in coherent pinned host memory; the persistent drain kernel claims cells
+// from the oldest request with unclaimed cells through one packed device
+// counter (request sequence number << 32 | next cell within the request).
+constexpr int kRing = 1024;   // ring slots: published requests in flight
+
+struct RingEntry {            // written by the host before publication
+  uint64_t arena_off;         // first arena cell of the request
+  uint64_t n;                 // cells (> 0)
+  double dt;                  // interval [s]
+  uint64_t seq;               // request sequence number
 };
+
 struct ServedArgs {
   Net net;
   Par par;
-  const Slot* slots;          // device copy of the slot table
-  const int32_t* item_slot;   // work item -> slot index
-  const int64_t* item_begin;  // work item -> first cell
-  const int32_t* item_count;  // work item -> number of cells
-  int64_t n_items;
-  unsigned long long* counter;      // work counter (items)
-  int32_t* slot_remaining;          // per slot: items left
+  Cells arena;                        // arena SoA arrays (n = capacity)
+  const RingEntry* ring;              // host-mapped, kRing entries
+  const uint64_t* published;          // host-mapped: requests published so far
+  unsigned long long* claim;          // device: packed claim cursor
+  int32_t* remaining;                 // device, per ring slot: cells not yet stored
+  uint64_t* done;                     // host-mapped, per ring slot: seq + 1 when complete
+  uint64_t idle_ticks;                // a wave with no work for this long exits
+  uint64_t life_ticks;                // no claims after this long (wall-clock ticks)
+  uint64_t backoff_ticks;             // wait between claims that found nothing
   int32_t refill_min;
+};
+
+// Copy of one request between caller buffers and the arena.
+struct CopyArgs {
+  Cells user;        // caller buffers (n = request cells)
+  Cells arena;       // arena arrays
+  int64_t off;       // first arena cell
+  double z_default;  // zmet when the caller passes none
+  int32_t* remaining_slot;  // copy-in: set to n (may be null)
+  int32_t ir_evolve;
 };
 
 // host-callable launchers (defined in sfk_li.hip)
 hipError_t launch_step(const Args& a, int precision, int grid, hipStream_t s);
 hipError_t launch_reset(unsigned long long* counter, hipStream_t s);
 int max_blocks_per_cu(int precision);
+int served_blocks_per_cu(int precision);
 hipError_t launch_served(const ServedArgs& a, int precision, int grid, hipStream_t s);
+hipError_t launch_copy_in(const CopyArgs& a, hipStream_t s);
+hipError_t launch_copy_out(const CopyArgs& a, hipStream_t s);
 
 constexpr int kBlock = 256;
 

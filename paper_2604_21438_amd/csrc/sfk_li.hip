@@ -980,6 +980,170 @@ __global__ __launch_bounds__(kBlock) void li_step_kernel(Args a) {
   }
 }
 
+// ------------------------------------------------------------------ served
+// Claim up to `want` cells for one wave from the oldest published request
+// that still has unclaimed cells.  Executed by one lane.  The cursor packs
+// (request sequence << 32 | next cell) and only ever increases, so a
+// compare-and-swap on a stale value fails instead of claiming twice, and a
+// ring entry read through a stale cursor is never used.
+struct Claim {
+  uint64_t seq, first, off;
+  double dt;
+  int take;
+};
+
+__device__ inline uint64_t sys_load(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__device__ Claim claim_cells(const ServedArgs& a, int want) {
+  Claim c{0, 0, 0, 0.0, 0};
+  unsigned long long cur = __hip_atomic_load(a.claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int attempt = 0; attempt < 64; ++attempt) {
+    const uint64_t k = cur >> 32, o = cur & 0xffffffffull;
+    const uint64_t pub =
+        __hip_atomic_load(a.published, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (k >= pub) return c;
+    const RingEntry* e = a.ring + (k % kRing);
+    const uint64_t n = sys_load(&e->n);
+    const uint64_t seq = sys_load(&e->seq);
+    if (seq != k || o >= n) {  // stale cursor: the entry was reused meanwhile
+      cur = __hip_atomic_load(a.claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      continue;
+    }
+    const uint64_t take = (n - o) < uint64_t(want) ? (n - o) : uint64_t(want);
+    const unsigned long long nxt = (o + take == n) ? ((k + 1) << 32) : (cur + take);
+    if (__hip_atomic_compare_exchange_strong(a.claim, &cur, nxt, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+      c.seq = k;
+      c.first = o;
+      c.off = sys_load(&e->arena_off);
+      c.dt = __longlong_as_double((long long)sys_load(reinterpret_cast<const uint64_t*>(&e->dt)));
+      c.take = int(take);
+      return c;
+    }
+  }
+  return c;
+}
+
+// A lane has stored (or rejected) a cell of request `seq`: count it off; the
+// lane that stores the request's last cell reports completion to the host.
+__device__ inline void cell_done(const ServedArgs& a, uint64_t seq) {
+  const int slot = int(seq % kRing);
+  const int left = __hip_atomic_fetch_add(a.remaining + slot, -1, __ATOMIC_ACQ_REL,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+  if (left == 1)
+    __hip_atomic_store(a.done + slot, seq + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Persistent drain: lanes refill from the request ring as they finish;
+// every cell is advanced by its own request's dt with the same per-lane
+// code as the plain step, so a cell's result does not depend on which
+// requests share the device with it.  A wave leaves once it has been idle
+// for idle_ticks with nothing to claim, or once its lifetime is over and
+// its lanes are done (each cell is bounded by n_sub_max subcycles).
+template <class R>
+__global__ __launch_bounds__(kBlock) void served_drain_kernel(ServedArgs a) {
+  const int lane = threadIdx.x & 63;
+  int64_t cell = -1;
+  uint64_t seq = 0;
+  Lane L;
+  const uint64_t t0 = (uint64_t)wall_clock64();
+  uint64_t next_try = t0, last_work = t0;
+  bool closing = false;
+  for (;;) {
+    const unsigned long long idle = __ballot(cell < 0);
+    const unsigned long long busy = __ballot(cell >= 0);
+    const int nidle = __popcll(idle);
+    const uint64_t now = (uint64_t)wall_clock64();
+    if (now - t0 > a.life_ticks) closing = true;
+    if (!closing && nidle > 0 && (nidle >= a.refill_min || busy == 0) && now >= next_try) {
+      const int leader = __ffsll((long long)idle) - 1;
+      Claim c{0, 0, 0, 0.0, 0};
+      if (lane == leader) c = claim_cells(a, nidle);
+      const int take = __shfl(c.take, leader);
+      if (take == 0) {
+        next_try = now + a.backoff_ticks;
+        if (busy == 0) {
+          if (now - last_work > a.idle_ticks) break;
+          __builtin_amdgcn_s_sleep(32);
+        }
+        continue;
+      }
+      last_work = now;
+      const uint64_t cseq = __shfl(c.seq, leader);
+      const uint64_t first = __shfl(c.first, leader);
+      const uint64_t off = __shfl(c.off, leader);
+      const double dt = __shfl(c.dt, leader);
+      // order the arena reads after the request's publication
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+      if (cell < 0) {
+        const unsigned r = lanes_below(idle);
+        if (r < unsigned(take)) {
+          cell = int64_t(off + first + r);
+          seq = cseq;
+          if (!load_cell<R>(a.net, a.par, a.arena, cell, dt, L)) {
+            cell = -1;
+            cell_done(a, seq);
+          }
+        }
+      }
+      continue;
+    }
+    if (busy == 0) {
+      if (closing || now - last_work > a.idle_ticks) break;
+      __builtin_amdgcn_s_sleep(32);
+      continue;
+    }
+    if (cell >= 0) {
+      if (subcycle<R>(a.net, a.par, L)) {
+        store_cell<R>(a.net, a.par, a.arena, cell, L);
+        cell = -1;
+        cell_done(a, seq);
+      }
+    }
+  }
+}
+
+// Arena <-> caller copies of one request (grid-stride over its cells).
+__global__ __launch_bounds__(256) void copy_in_kernel(CopyArgs a) {
+  const int64_t n = a.user.n;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && a.remaining_slot) *a.remaining_slot = int32_t(n);
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t j = a.off + i;
+    a.arena.y_h2[j] = a.user.y_h2[i];
+    a.arena.y_e[j] = a.user.y_e[i];
+    a.arena.eint[j] = a.user.eint[i];
+    a.arena.tdust[j] = a.user.tdust[i];
+    if (a.ir_evolve) a.arena.eir[j] = a.user.eir[i];
+    const_cast<double*>(a.arena.nh)[j] = a.user.nh[i];
+    const_cast<double*>(a.arena.n_euv)[j] = a.user.n_euv[i];
+    const_cast<double*>(a.arena.n_fuv)[j] = a.user.n_fuv[i];
+    const_cast<double*>(a.arena.zmet)[j] = a.user.zmet ? a.user.zmet[i] : a.z_default;
+  }
+}
+
+__global__ __launch_bounds__(256) void copy_out_kernel(CopyArgs a) {
+  const int64_t n = a.user.n;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t j = a.off + i;
+    a.user.y_h2[i] = a.arena.y_h2[j];
+    a.user.y_e[i] = a.arena.y_e[j];
+    a.user.eint[i] = a.arena.eint[j];
+    a.user.tdust[i] = a.arena.tdust[j];
+    if (a.ir_evolve) a.user.eir[i] = a.arena.eir[j];
+    if (a.user.y_h) a.user.y_h[i] = a.arena.y_h[j];
+    if (a.user.y_hp) a.user.y_hp[i] = a.arena.y_hp[j];
+    if (a.user.y_hm) a.user.y_hm[i] = a.arena.y_hm[j];
+    if (a.user.tgas) a.user.tgas[i] = a.arena.tgas[j];
+    if (a.user.nsub) a.user.nsub[i] = a.arena.nsub[j];
+    if (a.user.niter) a.user.niter[i] = a.arena.niter[j];
+    if (a.user.flags) a.user.flags[i] = a.arena.flags[j];
+  }
+}
+
 __global__ void reset_kernel(unsigned long long* counter) { *counter = 0ull; }
 
 }  // namespace
@@ -1006,9 +1170,38 @@ int max_blocks_per_cu(int precision) {
   return nb > 0 ? nb : 1;
 }
 
+int served_blocks_per_cu(int precision) {
+  int nb = 0;
+  if (precision == 1)
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, served_drain_kernel<float>, kBlock, 0);
+  else
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, served_drain_kernel<double>, kBlock, 0);
+  return nb > 0 ? nb : 1;
+}
+
 hipError_t launch_served(const ServedArgs& a, int precision, int grid, hipStream_t s) {
-  (void)a; (void)precision; (void)grid; (void)s;
-  return hipErrorNotSupported;
+  if (precision == 1)
+    hipLaunchKernelGGL(served_drain_kernel<float>, dim3(grid), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(served_drain_kernel<double>, dim3(grid), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+namespace {
+int copy_grid(int64_t n) {
+  const int64_t g = (n + 255) / 256;
+  return int(g < 512 ? (g > 0 ? g : 1) : 512);
+}
+}  // namespace
+
+hipError_t launch_copy_in(const CopyArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(copy_in_kernel, dim3(copy_grid(a.user.n)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_out(const CopyArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(copy_out_kernel, dim3(copy_grid(a.user.n)), dim3(256), 0, s, a);
+  return hipGetLastError();
 }
 
 }  // namespace sfk

@@ -22,7 +22,10 @@ struct Config {
 
 struct Server;
 
-Server* create(const Config& cfg, std::string* err);
+// Allocates the arena (budget_bytes of device memory), the pinned request
+// rings and the drain graphs, and starts the scheduler thread.
+Server* create(const Config& cfg, std::string* err, int* code);
+int64_t capacity(const Server* s);  // arena capacity in cells
 int submit(Server* s, const sfc_request& req, uint64_t* ticket, std::string* err);
 int poll(Server* s, uint64_t ticket, sfc_result* out);
 int drain(Server* s, std::string* err);

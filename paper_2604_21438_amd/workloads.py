@@ -178,3 +178,45 @@ def grid256(n: int | None = None, side: int = 256):
     sl = slice(0, m)
     return _pack(nh[sl], n_euv, n_fuv, np.ones(m), y_h2[sl], y_e[sl], tg[sl], tg[sl].copy()), \
         10.0 * KYR
+
+
+BLOCK = 8  # AMR block edge (8^3 = 512 cells)
+
+
+def amr_requests(n_req: int, max_blocks: int = 4096, side: int = 256, n_levels: int = 6,
+                 seed_offset: int = 0):
+    """Served workload: n_req requests, each a set of 8^3-cell blocks cut
+    at seeded block-aligned offsets out of the grid256 fields (on a side^3
+    grid), with the block count floor(exp(U[0, ln(max_blocks + 1)])) in
+    [1, max_blocks], AMR level L ~ U{0..n_levels-1} and dt = 10 kyr / 2^L.
+
+    Returns (requests, field) where each request is a dict with 'cells'
+    (SoA dict, blocks concatenated, x-fastest inside a block), 'dt',
+    'level' and 'blocks' (block indices into the field)."""
+    field, dt0 = grid256(side=side)
+    g = _streams(3, 3, seed_offset)
+    nbmax = int(max_blocks)
+    nblk = np.floor(np.exp(g[0].uniform(0.0, np.log(nbmax + 1.0), n_req))).astype(np.int64)
+    nblk = np.clip(nblk, 1, nbmax)
+    level = g[1].integers(0, n_levels, n_req)
+    nb = side // BLOCK
+    # cell offsets of one block relative to its first cell
+    i = np.arange(BLOCK ** 3)
+    local = (i % BLOCK) + side * ((i // BLOCK) % BLOCK) + side * side * (i // (BLOCK * BLOCK))
+    reqs = []
+    for j in range(n_req):
+        b = g[2].integers(0, nb ** 3, int(nblk[j]))
+        bx, by, bz = b % nb, (b // nb) % nb, b // (nb * nb)
+        first = BLOCK * (bx + side * by + side * side * bz)
+        idx = (first[:, None] + local[None, :]).reshape(-1)
+        cells = {k: np.ascontiguousarray(v[idx]) for k, v in field.items()}
+        reqs.append(dict(cells=cells, dt=dt0 / 2.0 ** int(level[j]), level=int(level[j]),
+                         blocks=b))
+    return reqs, field
+
+
+def poisson_arrivals(n: int, rate: float, seed: int = 3):
+    """Arrival times [s] of a Poisson process of the given rate, from 0."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(21438 + seed)))
+    gaps = rng.exponential(1.0 / rate, n)
+    return np.concatenate([[0.0], np.cumsum(gaps[1:])])

@@ -87,3 +87,45 @@ def report(errs, exc, n, label="", gpu=None, ref=None, cells=None):
                   f"T {gpu['tgas'][i]:.6e}/{ref['tgas'][i]:.6e} y_h2 {gpu['y_h2'][i]:.6e}/{ref['y_h2'][i]:.6e}"
                   + extra, flush=True)
     sys.stdout.flush()
+
+
+FP64_TOL = 1e-9
+WELL_CONDITIONED = 1e-12
+SPREAD_FACTOR = 1000.0
+
+
+def worst_of(errs, n):
+    w = np.zeros(n)
+    for v in errs.values():
+        w = np.maximum(w, np.nan_to_num(v, nan=np.inf))
+    return w
+
+
+def assert_fp64_parity(gpu, cells, dt, onet, opar, label=""):
+    """The binary64 bar: cells the reference determines to 1e-12 (rounding
+    spread over three other valid roundings of the reference) match to
+    1e-9 with identical subcycle counts and flags; the others match to
+    max(1e-9, 1000 x spread).  Returns the reference outputs."""
+    ref = run_oracle(cells, dt, onet, opar)
+    spread = oracle.rounding_spread(cells, dt, ref, onet, opar, host_threads())
+    errs, exc = compare(gpu, ref)
+    n = cells["nh"].shape[0]
+    report(errs, exc, n, label, gpu, ref, cells)
+    worst = worst_of(errs, n)
+    wc = spread <= WELL_CONDITIONED
+    ic = ~wc
+    ratio = worst[ic] / np.maximum(spread[ic], 1e-300) if ic.any() else np.zeros(0)
+    print(f"[parity] {label}: well-conditioned {int(wc.sum())}/{n}, max err "
+          f"{worst[wc].max() if wc.any() else 0:.2e}; ill-conditioned {int(ic.sum())}, beyond "
+          f"1e-9: {int((worst[ic] > FP64_TOL).sum())}, max err/spread "
+          f"{ratio.max() if ratio.size else 0:.1f}", flush=True)
+    if wc.any():
+        i = int(np.argmax(np.where(wc, worst, 0)))
+        assert worst[wc].max() <= FP64_TOL, (label, "well-conditioned", i, worst[i], spread[i])
+        np.testing.assert_array_equal(gpu["nsub"][wc], ref["nsub"][wc])
+        np.testing.assert_array_equal(gpu["flags"][wc], ref["flags"][wc])
+    if ic.any():
+        tol = np.maximum(FP64_TOL, SPREAD_FACTOR * spread[ic])
+        bad = np.nonzero(worst[ic] > tol)[0]
+        assert bad.size == 0, (label, "ill-conditioned", np.nonzero(ic)[0][bad][:5])
+    return ref

@@ -1,0 +1,176 @@
+"""Served form (continuous batching) through the C ABI.
+
+Each request is a set of 8^3 AMR blocks with its own dt (10 kyr / 2^L).
+The contract checked here: a request's per-cell result is bitwise the same
+whether it runs alone or mixed with other requests of other sizes, levels
+and precisions, under any HBM budget; the binary64 served results meet the
+same bar against the CPU reference as the plain step; requests larger than
+the budget, bad arguments and unknown tickets are rejected with their
+status codes.
+"""
+import numpy as np
+import pytest
+
+from parity_util import assert_fp64_parity, oracle_net_params
+from paper_2604_21438_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("y_h2", "y_e", "eint", "tdust", "y_h", "y_hp", "y_hm", "tgas", "nsub", "niter", "flags")
+MIB = 1 << 20
+
+
+def _sfc():
+    import paper_2604_21438_amd as sfc
+    return sfc
+
+
+def _requests(n=12, max_blocks=8, side=32, seed_offset=0):
+    reqs, _ = W.amr_requests(n, max_blocks=max_blocks, side=side, seed_offset=seed_offset)
+    return reqs
+
+
+def _run_served(ctx, reqs, precisions, label):
+    """Submit every request back to back, drain, return host outputs."""
+    import torch
+    sfc = _sfc()
+    print(f"[served] {label}: {len(reqs)} requests, "
+          f"{sum(r['cells']['nh'].shape[0] for r in reqs)} cells", flush=True)
+    bufs = [sfc.to_device(r["cells"]) for r in reqs]
+    torch.cuda.synchronize()
+    tickets = [ctx.submit(b, r["dt"], p, level=r["level"], tag=i)
+               for i, (b, r, p) in enumerate(zip(bufs, reqs, precisions))]
+    ctx.drain()
+    res = [ctx.poll(t) for t in tickets]
+    for i, r in enumerate(res):
+        assert r is not None and r["status"] == 0 and r["tag"] == i
+        assert r["t_submit"] <= r["t_admit"] <= r["t_done"]
+        assert r["cells"] == reqs[i]["cells"]["nh"].shape[0]
+    torch.cuda.synchronize()
+    return [{k: v.cpu().numpy() for k, v in b.items()} for b in bufs]
+
+
+def _alone(ctx, reqs, precisions):
+    return [_run_served(ctx, [r], [p], f"alone {i}")[0]
+            for i, (r, p) in enumerate(zip(reqs, precisions))]
+
+
+def _same(a, b, label):
+    for k in KEYS:
+        x, y = a[k], b[k]
+        if x.dtype.kind == "f":
+            same = (x.view(np.int64) == y.view(np.int64))
+        else:
+            same = x == y
+        assert same.all(), (label, k, int((~same).sum()))
+
+
+def test_served_alone_equals_mixed_bitwise():
+    """FP64 and mixed requests interleaved, all admitted together."""
+    sfc = _sfc()
+    reqs = _requests(12)
+    prec = [sfc.FP64 if i % 3 else sfc.MIXED for i in range(len(reqs))]
+    ctx = sfc.Context(served_budget_bytes=256 * MIB)
+    try:
+        alone = _alone(ctx, reqs, prec)
+        mixed = _run_served(ctx, reqs, prec, "mix")
+        # the same requests again, behind other traffic
+        extra = _requests(6, seed_offset=7)
+        both = _run_served(ctx, extra + reqs, [sfc.MIXED] * 6 + prec, "mix behind traffic")[6:]
+    finally:
+        ctx.close()
+    for i in range(len(reqs)):
+        _same(alone[i], mixed[i], f"request {i} mix")
+        _same(alone[i], both[i], f"request {i} behind traffic")
+
+
+def test_served_tight_budget_queues_and_matches():
+    """A budget of a few requests forces admission to wait for memory."""
+    sfc = _sfc()
+    reqs = _requests(10, max_blocks=16, seed_offset=1)
+    biggest = max(r["cells"]["nh"].shape[0] for r in reqs)
+    budget = 2 * biggest * 108 + 64 * 108  # arena cells are 108 bytes in FIXED IR mode
+    prec = [sfc.FP64] * len(reqs)
+    big = sfc.Context(served_budget_bytes=256 * MIB)
+    try:
+        alone = _alone(big, reqs, prec)
+    finally:
+        big.close()
+    small = sfc.Context(served_budget_bytes=budget)
+    try:
+        queued = _run_served(small, reqs, prec, f"budget {budget} B")
+    finally:
+        small.close()
+    for i in range(len(reqs)):
+        _same(alone[i], queued[i], f"request {i} tight budget")
+
+
+def test_served_fp64_matches_reference():
+    """Served binary64 results against the CPU reference, request by request
+    (each with its own dt), to the plain step's bar."""
+    sfc = _sfc()
+    reqs = _requests(4, max_blocks=2, seed_offset=2)
+    ctx = sfc.Context(served_budget_bytes=64 * MIB)
+    try:
+        out = _run_served(ctx, reqs, [sfc.FP64] * len(reqs), "vs reference")
+    finally:
+        ctx.close()
+    onet, opar = oracle_net_params(sfc.default_network(), sfc.default_params(), 1.0)
+    for i, (r, o) in enumerate(zip(reqs, out)):
+        o["flags"] = o["flags"].view(np.uint32)
+        assert_fp64_parity(o, r["cells"], r["dt"], onet, opar,
+                           f"served request {i} level {r['level']}")
+
+
+def test_served_matches_plain_step():
+    """The served drain runs the plain step's per-lane code: same bits."""
+    import torch
+    sfc = _sfc()
+    reqs = _requests(6, max_blocks=4, seed_offset=3)
+    ctx = sfc.Context(served_budget_bytes=64 * MIB)
+    try:
+        for prec in (sfc.FP64, sfc.MIXED):
+            served = _run_served(ctx, reqs, [prec] * len(reqs), f"served prec {prec}")
+            for i, r in enumerate(reqs):
+                t = sfc.to_device(r["cells"])
+                ctx.step(t, r["dt"], prec)
+                torch.cuda.synchronize()
+                plain = {k: v.cpu().numpy() for k, v in t.items()}
+                _same(served[i], plain, f"request {i} prec {prec} served vs plain")
+    finally:
+        ctx.close()
+
+
+def test_served_errors_and_tickets():
+    import torch
+    sfc = _sfc()
+    reqs = _requests(2, max_blocks=4, seed_offset=4)
+    plain = sfc.Context()
+    try:
+        b = sfc.to_device(reqs[0]["cells"])
+        with pytest.raises(sfc.SfcError, match=r"\(-7\)"):
+            plain.submit(b, reqs[0]["dt"])
+    finally:
+        plain.close()
+    ctx = sfc.Context(served_budget_bytes=1 * MIB)  # ~9700 cells
+    try:
+        big = W.uniform_population(20000)
+        tb = sfc.to_device(big)
+        with pytest.raises(sfc.SfcError, match=r"\(-3\)"):
+            ctx.submit(tb, 1e10)
+        b = sfc.to_device(reqs[1]["cells"])
+        with pytest.raises(sfc.SfcError, match=r"\(-1\)"):
+            ctx.submit(b, -1.0)
+        with pytest.raises(sfc.SfcError, match=r"\(-1\)"):
+            ctx.submit(b, 1e10, precision=7)
+        with pytest.raises(sfc.SfcError, match=r"\(-1\)"):
+            ctx.poll(123456)
+        torch.cuda.synchronize()
+        t = ctx.submit(b, reqs[1]["dt"], sfc.FP64)
+        ctx.drain()
+        r = ctx.poll(t)
+        assert r is not None and r["status"] == 0
+        with pytest.raises(sfc.SfcError, match=r"\(-1\)"):
+            ctx.poll(t)  # a ticket is released once reported
+    finally:
+        ctx.close()
