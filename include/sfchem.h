@@ -32,7 +32,9 @@
 extern "C" {
 #endif
 
-#define SFC_ABI_VERSION 1u
+/* Version of sfc_network and sfc_params (both checked through
+ * sfc_network.abi_version). */
+#define SFC_ABI_VERSION 2u
 
 enum {
   SFC_OK = 0,
@@ -49,6 +51,11 @@ typedef enum { SFC_FP64 = 0, SFC_MIXED = 1 } sfc_precision;
 typedef enum { SFC_IR_FIXED = 0, SFC_IR_EVOLVE = 1 } sfc_ir_mode;
 typedef enum { SFC_THERMAL_EVOLVE = 0, SFC_THERMAL_ISOTHERMAL = 1 } sfc_thermal_mode;
 typedef enum { SFC_DUST_EVOLVE = 0, SFC_DUST_FROZEN = 1 } sfc_dust_mode;
+/* Order in which the plain step hands cells to GPU lanes (scheduling only;
+ * every cell's result is the same in both).  DENSITY starts the densest
+ * cells first: their stiffer chemistry and gas-grain coupling need the most
+ * subcycles, and starting them early keeps them off the end of the call. */
+typedef enum { SFC_DISPATCH_INDEX = 0, SFC_DISPATCH_DENSITY = 1 } sfc_dispatch;
 
 enum { SFC_NREAC = 12, SFC_NPROC = 14, SFC_NLINE = 5 };
 
@@ -96,6 +103,7 @@ typedef struct {
   int32_t ir_mode;     /* sfc_ir_mode [SFC_IR_FIXED]                      */
   int32_t thermal_mode;/* sfc_thermal_mode [SFC_THERMAL_EVOLVE]           */
   int32_t dust_mode;   /* sfc_dust_mode [SFC_DUST_EVOLVE]                 */
+  int32_t dispatch;    /* sfc_dispatch [SFC_DISPATCH_DENSITY]             */
 } sfc_params;
 
 void sfc_network_default(sfc_network* net);

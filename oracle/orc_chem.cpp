@@ -26,7 +26,7 @@
  *                      = 20, substeps of Eq. substep_NRchem.
  *
  * Readings where the paper is silent, garbled or points to other papers are
- * listed where they are used ("Reading:") and collected in the design doc.
+ * listed where they are used ("Reading:").
  * Stand-ins for formulas the paper does not print are labelled "STAND-IN".
  *
  * Pins (tests/test_oracle_*.py): rate values printed by the paper (H II

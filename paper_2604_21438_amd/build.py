@@ -18,6 +18,11 @@ LIB = os.path.join(PKG, "libsfchem.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["sfk_li.hip", "sfserve.cpp", "sfchem.cpp"]
+# Extra device flags per source.  The LI kernels run one cell per lane for
+# thousands of loop iterations; machine LICM hoists every loop-invariant
+# binary64 constant (and products of them) out of that loop into registers,
+# which doubles the kernel's VGPR use and halves its occupancy.
+EXTRA = {"sfk_li.hip": ["-mllvm", "-disable-machine-licm"]}
 ARCH = os.environ.get("SFC_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
@@ -33,7 +38,7 @@ def build(verbose: bool = False) -> str:
         path = os.path.join(CSRC, src)
         obj = os.path.join(BUILD, src + ".o")
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmd = ["hipcc", *FLAGS, *lang, "-c", path, "-o", obj]
+        cmd = ["hipcc", *FLAGS, *EXTRA.get(src, []), *lang, "-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), file=sys.stderr)
         subprocess.check_call(cmd)

@@ -107,6 +107,12 @@ struct sfc_ctx {
   sfk::Net net{};
   sfk::Par par{};
   unsigned long long* d_counter = nullptr;
+  sfk::Net* d_net = nullptr;  // device copies read by the kernels
+  sfk::Par* d_par = nullptr;
+  int dispatch = SFC_DISPATCH_DENSITY;
+  int32_t* d_order = nullptr;  // density dispatch: cell order and bucket counters
+  int64_t order_cap = 0;
+  uint32_t* d_buckets = nullptr;
   int cus = 0;
   int bpc[2] = {1, 1};
   int refill_min = 1;
@@ -127,6 +133,16 @@ struct DeviceGuard {
     if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
   }
 };
+
+// Frees a context's device buffers and the context itself.
+void release(sfc_ctx* ctx) {
+  if (ctx->d_order) (void)hipFree(ctx->d_order);
+  if (ctx->d_buckets) (void)hipFree(ctx->d_buckets);
+  if (ctx->d_counter) (void)hipFree(ctx->d_counter);
+  if (ctx->d_net) (void)hipFree(ctx->d_net);
+  if (ctx->d_par) (void)hipFree(ctx->d_par);
+  delete ctx;
+}
 
 int fail(sfc_ctx* ctx, int code, const std::string& msg) {
   if (ctx) ctx->last_error = msg;
@@ -216,6 +232,7 @@ void sfc_params_default(sfc_params* p) {
   p->ir_mode = SFC_IR_FIXED;
   p->thermal_mode = SFC_THERMAL_EVOLVE;
   p->dust_mode = SFC_DUST_EVOLVE;
+  p->dispatch = SFC_DISPATCH_DENSITY;
 }
 
 int sfc_chem_init(const sfc_network* net_in, double z_default, double dust_cap_factor,
@@ -238,6 +255,7 @@ int sfc_chem_init(const sfc_network* net_in, double z_default, double dust_cap_f
   sfk::Par kpar;
   if (!fill_net(net, knet) || !fill_par(p, z_default, dust_cap_factor * 1.0e4, knet, kpar))
     return SFC_E_INVAL;
+  if (p.dispatch != SFC_DISPATCH_INDEX && p.dispatch != SFC_DISPATCH_DENSITY) return SFC_E_INVAL;
   if (hip_device < 0) return SFC_E_INVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device >= ndev) return SFC_E_DEVICE;
@@ -246,6 +264,7 @@ int sfc_chem_init(const sfc_network* net_in, double z_default, double dust_cap_f
   ctx->device = hip_device;
   ctx->net = knet;
   ctx->par = kpar;
+  ctx->dispatch = p.dispatch;
   DeviceGuard g(hip_device);
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) {
@@ -259,9 +278,15 @@ int sfc_chem_init(const sfc_network* net_in, double z_default, double dust_cap_f
     delete ctx;
     return SFC_E_NOMEM;
   }
-  if (hipMemset(ctx->d_counter, 0, sizeof(unsigned long long)) != hipSuccess) {
-    (void)hipFree(ctx->d_counter);
-    delete ctx;
+  if (hipMalloc(&ctx->d_net, sizeof(sfk::Net)) != hipSuccess ||
+      hipMalloc(&ctx->d_par, sizeof(sfk::Par)) != hipSuccess) {
+    release(ctx);
+    return SFC_E_NOMEM;
+  }
+  if (hipMemset(ctx->d_counter, 0, sizeof(unsigned long long)) != hipSuccess ||
+      hipMemcpy(ctx->d_net, &ctx->net, sizeof(sfk::Net), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(ctx->d_par, &ctx->par, sizeof(sfk::Par), hipMemcpyHostToDevice) != hipSuccess) {
+    release(ctx);
     return SFC_E_DEVICE;
   }
   if (const char* e = std::getenv("SFC_REFILL_MIN")) {
@@ -276,12 +301,13 @@ int sfc_chem_init(const sfc_network* net_in, double z_default, double dust_cap_f
     sc.par = ctx->par;
     sc.cus = ctx->cus;
     sc.refill_min = ctx->refill_min;
+    sc.netc = ctx->d_net;
+    sc.parc = ctx->d_par;
     std::string err;
     int code = SFC_E_NOMEM;
     ctx->server = sfserve::create(sc, &err, &code);
     if (!ctx->server) {
-      (void)hipFree(ctx->d_counter);
-      delete ctx;
+      release(ctx);
       return code;
     }
   }
@@ -307,9 +333,30 @@ int sfc_chem_step(sfc_ctx* ctx, const sfc_cells* cells, double dt, int precision
   a.dt = dt;
   a.counter = ctx->d_counter;
   a.refill_min = ctx->refill_min;
+  a.netc = ctx->d_net;
+  a.parc = ctx->d_par;
   const int64_t need = (cells->n + sfk::kBlock - 1) / sfk::kBlock;
   const int64_t cap = int64_t(ctx->cus) * ctx->bpc[precision];
   const int grid = int(need < cap ? need : cap);
+  a.order = nullptr;
+  // density dispatch pays off once lanes take several cells each
+  if (ctx->dispatch == SFC_DISPATCH_DENSITY && cells->n > 2 * int64_t(grid) * sfk::kBlock &&
+      cells->n < (int64_t(1) << 31)) {
+    if (cells->n > ctx->order_cap) {
+      if (ctx->d_order) (void)hipFree(ctx->d_order);
+      ctx->d_order = nullptr;
+      ctx->order_cap = 0;
+      if (hipMalloc(&ctx->d_order, size_t(cells->n) * sizeof(int32_t)) != hipSuccess)
+        return fail(ctx, SFC_E_NOMEM, "sfc_chem_step: dispatch order buffer");
+      ctx->order_cap = cells->n;
+    }
+    if (!ctx->d_buckets &&
+        hipMalloc(&ctx->d_buckets, 2 * sfk::kOrderBuckets * sizeof(uint32_t)) != hipSuccess)
+      return fail(ctx, SFC_E_NOMEM, "sfc_chem_step: dispatch buckets");
+    const hipError_t oe = sfk::launch_order(cells->nh, cells->n, ctx->d_order, ctx->d_buckets, s);
+    if (oe != hipSuccess) return hip_fail(ctx, oe, "dispatch order launch");
+    a.order = ctx->d_order;
+  }
   hipError_t e = sfk::launch_reset(ctx->d_counter, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "reset launch");
   e = sfk::launch_step(a, precision, grid, s);
@@ -351,8 +398,8 @@ int sfc_chem_destroy(sfc_ctx* ctx) {
   if (!ctx) return SFC_OK;
   DeviceGuard g(ctx->device);
   if (ctx->server) sfserve::destroy(ctx->server);
-  if (ctx->d_counter) (void)hipFree(ctx->d_counter);
-  delete ctx;
+  ctx->server = nullptr;
+  release(ctx);
   return SFC_OK;
 }
 

@@ -53,6 +53,9 @@ struct Args {
   double dt;
   unsigned long long* counter;  // work counter, zero at launch
   int32_t refill_min;           // refill a wave once this many lanes are idle
+  const Net* netc;              // device copies of net and par (read-only)
+  const Par* parc;
+  const int32_t* order;         // lane work item -> cell (null: identity)
 };
 
 // Served form.  Requests are published by the host into a ring that lives
@@ -81,6 +84,8 @@ struct ServedArgs {
   uint64_t life_ticks;                // no claims after this long (wall-clock ticks)
   uint64_t backoff_ticks;             // wait between claims that found nothing
   int32_t refill_min;
+  const Net* netc;                    // device copies of net and par (read-only)
+  const Par* parc;
 };
 
 // Copy of one request between caller buffers and the arena.
@@ -101,6 +106,11 @@ int served_blocks_per_cu(int precision);
 hipError_t launch_served(const ServedArgs& a, int precision, int grid, hipStream_t s);
 hipError_t launch_copy_in(const CopyArgs& a, hipStream_t s);
 hipError_t launch_copy_out(const CopyArgs& a, hipStream_t s);
+// Density dispatch: order[0..n) = cells by decreasing half-octave of n_H
+// (counting sort; work holds 2 * kOrderBuckets counters, n < 2^31).
+constexpr int kOrderBuckets = 128;
+hipError_t launch_order(const double* nh, int64_t n, int32_t* order, uint32_t* work,
+                        hipStream_t s);
 
 constexpr int kBlock = 256;
 

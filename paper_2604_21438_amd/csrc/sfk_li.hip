@@ -123,19 +123,33 @@ __device__ inline G<R> quot(G<R> x, G<R> y) {
 // ------------------------------------------------------------------ rates
 // k_H2 (H + e -> H- + photon) and k_H3 (H- + H -> H2 + e), Table
 // "Chemical reactions"; powers of T through one shared ln T.
+// k_H3 fit: exponents a_i, coefficients c_i, and c_i a_i (for dk/dT)
+__constant__ double kH3[3][6] = {
+    {0.098493, 0.5561, 2.1826, 1.0461, 3.0424, 3.7741},
+    {1.0, 0.32852, 2.771e-7, 6.191e-3, 8.9712e-11, 3.2576e-14},
+    {0.098493, 0.32852 * 0.5561, 2.771e-7 * 2.1826, 6.191e-3 * 1.0461, 8.9712e-11 * 3.0424,
+     3.2576e-14 * 3.7741}};
+
 template <class R>
 __device__ inline void k2k3(double T, double lnT, double iT, TF<R>& k2, TF<R>& k3) {
   using M = Mth<R>;
   k2.v = M::ea(-41.11005943727161 + 0.928 * lnT - T * (1.0 / 16200.0));  // ln 1.4e-18
   k2.t = k2.v * R(0.928 * iT - 1.0 / 16200.0);
-  const R p1 = M::ea(0.098493 * lnT), p2 = M::ea(0.5561 * lnT);
-  const R p3 = M::ea(2.1826 * lnT), q1 = M::ea(1.0461 * lnT);
-  const R q2 = M::ea(3.0424 * lnT), q3 = M::ea(3.7741 * lnT);
-  const R N = p1 + R(0.32852) * p2 + R(2.771e-7) * p3;
-  const R D = R(1) + R(6.191e-3) * q1 + R(8.9712e-11) * q2 + R(3.2576e-14) * q3;
-  const R dN = R(0.098493) * p1 + R(0.32852 * 0.5561) * p2 + R(2.771e-7 * 2.1826) * p3;
-  const R dD = R(6.191e-3 * 1.0461) * q1 + R(8.9712e-11 * 3.0424) * q2 +
-               R(3.2576e-14 * 3.7741) * q3;
+  // N = T^a0 + c1 T^a1 + c2 T^a2 and D = 1 + c3 T^a3 + c4 T^a4 + c5 T^a5 one
+  // power at a time (kept rolled: six binary64 exponentials in flight
+  // cost registers that the whole subcycle pays for)
+  R N = R(0), dN = R(0), D = R(1), dD = R(0);
+#pragma unroll 1
+  for (int i = 0; i < 6; ++i) {
+    const R p = M::ea(kH3[0][i] * lnT);
+    if (i < 3) {
+      N = N + R(kH3[1][i]) * p;
+      dN = dN + R(kH3[2][i]) * p;
+    } else {
+      D = D + R(kH3[1][i]) * p;
+      dD = dD + R(kH3[2][i]) * p;
+    }
+  }
   const R iN = M::dv(R(1), N), iD = M::dv(R(1), D);
   k3.v = R(1.35e-9) * N * iD;
   k3.t = k3.v * (dN * iN - dD * iD) * R(iT);
@@ -391,7 +405,8 @@ __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, d
     acc(nel, n, TF<R>{s100, R(-0.5) * s100 * iT}, YE);
     const R xo = R(nt.x_o * ck.fd);
     const R m13 = -R(nt.pm[12]);
-#pragma unroll
+    // kept rolled: five interleaved copies of this body cost ~130 VGPRs
+#pragma unroll 1
     for (int j = 0; j < 5; ++j) {
       G<R> emit;
       if (j == 0) emit = Y2;
@@ -940,6 +955,24 @@ __device__ inline unsigned lanes_below(unsigned long long mask) {
   return __builtin_amdgcn_mbcnt_hi(unsigned(mask >> 32), __builtin_amdgcn_mbcnt_lo(unsigned(mask), 0u));
 }
 
+// The network and parameters are re-read from the context's device copy
+// (constant address space, scalar loads) at every subcycle.  Holding the
+// ~100 uniform binary64 values they feed across the whole cell loop costs
+// SGPR spills and VGPR copies; the opaque pointer keeps the loads (and the
+// arithmetic on them) inside the loop.
+typedef const __attribute__((address_space(4))) Net CNet;
+typedef const __attribute__((address_space(4))) Par CPar;
+__device__ inline const Net& fresh(const Net* p) {
+  CNet* q = (CNet*)p;
+  asm volatile("" : "+s"(q));
+  return *(const Net*)q;
+}
+__device__ inline const Par& fresh(const Par* p) {
+  CPar* q = (CPar*)p;
+  asm volatile("" : "+s"(q));
+  return *(const Par*)q;
+}
+
 // ------------------------------------------------------------------ kernels
 // Persistent lane-refill driver.  cell: >= 0 working, -1 idle, -2 retired
 // (the counter passed the end).  Every lane either works on a cell, whose
@@ -962,7 +995,7 @@ __global__ __launch_bounds__(kBlock) void li_step_kernel(Args a) {
       if (cell == -1) {
         const unsigned long long idx = base + lanes_below(idle);
         if (idx < (unsigned long long)a.c.n) {
-          cell = (int64_t)idx;
+          cell = a.order ? int64_t(a.order[idx]) : int64_t(idx);
           if (!load_cell<R>(a.net, a.par, a.c, cell, a.dt, L)) cell = -1;
         } else {
           cell = -2;
@@ -972,7 +1005,7 @@ __global__ __launch_bounds__(kBlock) void li_step_kernel(Args a) {
     }
     if (busy == 0) break;
     if (cell >= 0) {
-      if (subcycle<R>(a.net, a.par, L)) {
+      if (subcycle<R>(fresh(a.netc), fresh(a.parc), L)) {
         store_cell<R>(a.net, a.par, a.c, cell, L);
         cell = -1;
       }
@@ -1096,12 +1129,73 @@ __global__ __launch_bounds__(kBlock) void served_drain_kernel(ServedArgs a) {
       continue;
     }
     if (cell >= 0) {
-      if (subcycle<R>(a.net, a.par, L)) {
+      if (subcycle<R>(fresh(a.netc), fresh(a.parc), L)) {
         store_cell<R>(a.net, a.par, a.arena, cell, L);
         cell = -1;
         cell_done(a, seq);
       }
     }
+  }
+}
+
+// ------------------------------------------------------------------ dispatch
+// Counting sort of the cells by half-octave of n_H, densest first.  Invalid
+// densities (non-positive, NaN) go to the last bucket.
+__device__ inline int density_bucket(double nh) {
+  if (!(nh > 0.0) || !(nh < 1.0e300)) return 0;
+  const float l2 = __builtin_amdgcn_logf(float(nh));  // log2, binary32 is plenty
+  int b = int(floorf(2.0f * l2)) + kOrderBuckets / 2;
+  return b < 0 ? 0 : (b >= kOrderBuckets ? kOrderBuckets - 1 : b);
+}
+
+__global__ __launch_bounds__(256) void order_zero_kernel(uint32_t* work) {
+  for (int t = threadIdx.x; t < 2 * kOrderBuckets; t += blockDim.x) work[t] = 0u;
+}
+
+__global__ __launch_bounds__(256) void order_count_kernel(const double* nh, int64_t n,
+                                                          uint32_t* hist) {
+  __shared__ uint32_t h[kOrderBuckets];
+  for (int t = threadIdx.x; t < kOrderBuckets; t += blockDim.x) h[t] = 0u;
+  __syncthreads();
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    atomicAdd(&h[density_bucket(nh[i])], 1u);
+  __syncthreads();
+  for (int t = threadIdx.x; t < kOrderBuckets; t += blockDim.x)
+    if (h[t]) atomicAdd(&hist[t], h[t]);
+}
+
+// offs[b] = number of cells in buckets above b (one thread; 128 entries)
+__global__ void order_scan_kernel(const uint32_t* hist, uint32_t* offs) {
+  if (threadIdx.x != 0) return;
+  uint32_t sum = 0u;
+  for (int b = kOrderBuckets - 1; b >= 0; --b) {
+    offs[b] = sum;
+    sum += hist[b];
+  }
+}
+
+// Each block reserves one range per bucket for its own cells (same
+// grid-stride set as the count), then places them.
+__global__ __launch_bounds__(256) void order_scatter_kernel(const double* nh, int64_t n,
+                                                            uint32_t* offs, int32_t* order) {
+  __shared__ uint32_t cnt[kOrderBuckets], base[kOrderBuckets];
+  for (int t = threadIdx.x; t < kOrderBuckets; t += blockDim.x) cnt[t] = 0u;
+  __syncthreads();
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    atomicAdd(&cnt[density_bucket(nh[i])], 1u);
+  __syncthreads();
+  for (int t = threadIdx.x; t < kOrderBuckets; t += blockDim.x) {
+    base[t] = cnt[t] ? atomicAdd(&offs[t], cnt[t]) : 0u;
+    cnt[t] = 0u;
+  }
+  __syncthreads();
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int b = density_bucket(nh[i]);
+    const uint32_t r = atomicAdd(&cnt[b], 1u);
+    order[base[b] + r] = int32_t(i);
   }
 }
 
@@ -1193,6 +1287,18 @@ int copy_grid(int64_t n) {
   return int(g < 512 ? (g > 0 ? g : 1) : 512);
 }
 }  // namespace
+
+hipError_t launch_order(const double* nh, int64_t n, int32_t* order, uint32_t* work,
+                        hipStream_t s) {
+  const int64_t g = (n + 255) / 256;
+  const int grid = int(g < 1024 ? (g > 0 ? g : 1) : 1024);
+  hipLaunchKernelGGL(order_zero_kernel, dim3(1), dim3(256), 0, s, work);
+  hipLaunchKernelGGL(order_count_kernel, dim3(grid), dim3(256), 0, s, nh, n, work);
+  hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(64), 0, s, work, work + kOrderBuckets);
+  hipLaunchKernelGGL(order_scatter_kernel, dim3(grid), dim3(256), 0, s, nh, n,
+                     work + kOrderBuckets, order);
+  return hipGetLastError();
+}
 
 hipError_t launch_copy_in(const CopyArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(copy_in_kernel, dim3(copy_grid(a.user.n)), dim3(256), 0, s, a);

@@ -487,6 +487,8 @@ Server* create(const Config& cfg, std::string* err, int* code) {
     a.life_ticks = uint64_t(env_num("SFC_SERVE_LIFE_S", 30.0) * tps);
     a.backoff_ticks = uint64_t(20e-6 * tps);
     a.refill_min = cfg.refill_min;
+    a.netc = cfg.netc;
+    a.parc = cfg.parc;
     q.grid = cus * sfk::served_blocks_per_cu(prec);
     if (hipStreamBeginCapture(s->drain_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return fail(s, SFC_E_DEVICE, "graph capture");

@@ -18,6 +18,8 @@ struct Config {
   sfk::Par par{};
   int cus = 0;
   int refill_min = 1;
+  const sfk::Net* netc = nullptr;  // device copies owned by the context
+  const sfk::Par* parc = nullptr;
 };
 
 struct Server;

@@ -52,3 +52,13 @@ def test_strerror_and_init_errors_without_device():
     assert L.sfc_chem_init(C.byref(net), 1.0, 1.0, None, 0, 0, C.byref(h)) == sfc.E_VERSION
     assert L.sfc_chem_destroy(None) == sfc.OK
     assert L.sfc_chem_step(None, None, 1.0, 0, None) == sfc.E_INVAL
+
+
+def test_dispatch_default_and_validation():
+    import paper_2604_21438_amd as sfc
+    L = sfc.lib()
+    p = sfc.default_params()
+    assert p.dispatch == sfc.DISPATCH_DENSITY
+    p.dispatch = 7
+    h = C.c_void_p()
+    assert L.sfc_chem_init(None, 1.0, 1.0, C.byref(p), 0, 0, C.byref(h)) == sfc.E_INVAL
