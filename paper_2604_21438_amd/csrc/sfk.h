@@ -59,16 +59,18 @@ struct Args {
 };
 
 // Served form.  Requests are published by the host into a ring that lives
-// in coherent pinned host memory; the persistent drain kernel claims cells
-// from the oldest request with unclaimed cells through one packed device
-// counter (request sequence number << 32 | next cell within the request).
-constexpr int kRing = 1024;   // ring slots: published requests in flight
+// in coherent pinned host memory.  Waves claim cells of the oldest request
+// with unclaimed cells: a device head index names that request, and a
+// per-slot device counter hands out its cells with one atomicAdd.  A slot
+// is reused only kRing requests later, long after every wave has moved past
+// it.  The lane that stores a request's last cell raises its done word.
+constexpr int kRing = 65536;   // ring slots
 
 struct RingEntry {            // written by the host before publication
   uint64_t arena_off;         // first arena cell of the request
   uint64_t n;                 // cells (> 0)
   double dt;                  // interval [s]
-  uint64_t seq;               // request sequence number
+  uint64_t seq;               // request sequence number (written last)
 };
 
 struct ServedArgs {
@@ -77,12 +79,14 @@ struct ServedArgs {
   Cells arena;                        // arena SoA arrays (n = capacity)
   const RingEntry* ring;              // host-mapped, kRing entries
   const uint64_t* published;          // host-mapped: requests published so far
-  unsigned long long* claim;          // device: packed claim cursor
+  unsigned long long* head;           // device: oldest request that may have unclaimed cells
+  uint32_t* claimed;                  // device, per ring slot: cells handed out
   int32_t* remaining;                 // device, per ring slot: cells not yet stored
   uint64_t* done;                     // host-mapped, per ring slot: seq + 1 when complete
   uint64_t idle_ticks;                // a wave with no work for this long exits
   uint64_t life_ticks;                // no claims after this long (wall-clock ticks)
-  uint64_t backoff_ticks;             // wait between claims that found nothing
+  uint64_t backoff_ticks;             // first wait after a claim that found nothing
+  uint64_t backoff_max_ticks;         // waits double up to this
   int32_t refill_min;
   const Net* netc;                    // device copies of net and par (read-only)
   const Par* parc;
@@ -95,6 +99,7 @@ struct CopyArgs {
   int64_t off;       // first arena cell
   double z_default;  // zmet when the caller passes none
   int32_t* remaining_slot;  // copy-in: set to n (may be null)
+  uint32_t* claimed_slot;   // copy-in: set to 0 (may be null)
   int32_t ir_evolve;
 };
 

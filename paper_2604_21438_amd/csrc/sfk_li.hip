@@ -49,6 +49,16 @@ constexpr double TLOW = 75.0;
 constexpr double EVK = 1.602176634e-12 / 1.380649e-16;  // eV / k_B [K]
 
 // ------------------------------------------------------------------ math
+// 1/x for positive, finite, normal x: hardware estimate and two Newton
+// steps (within an ulp; an IEEE divide costs about twice the instructions).
+__device__ inline double frcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 template <class R>
 struct Mth;
 template <>
@@ -58,7 +68,8 @@ struct Mth<double> {
   __device__ static double lg(double x) { return log(x); }
   __device__ static double lg1p(double x) { return log1p(x); }
   __device__ static double sq(double x) { return sqrt(x); }
-  __device__ static double dv(double a, double b) { return a / b; }
+  // every quotient in the assembly has a positive, normal denominator
+  __device__ static double dv(double a, double b) { return a * frcp(b); }
 };
 template <>
 struct Mth<float> {
@@ -531,8 +542,9 @@ __device__ inline void solve3(double a00, double a01, double a02, double a10, do
     a10 = n1[0]; a11 = n1[1]; a12 = n1[2]; b1 = n1[3];
     a20 = n2[0]; a21 = n2[1]; a22 = n2[2]; b2 = n2[3];
   }
+  const double i00 = frcp(a00);
   {
-    const double m1 = a10 / a00, m2 = a20 / a00;
+    const double m1 = a10 * i00, m2 = a20 * i00;
     a11 = a11 - m1 * a01; a12 = a12 - m1 * a02; b1 = b1 - m1 * b0;
     a21 = a21 - m2 * a01; a22 = a22 - m2 * a02; b2 = b2 - m2 * b0;
   }
@@ -542,14 +554,15 @@ __device__ inline void solve3(double a00, double a01, double a02, double a10, do
     t = a12; a12 = a22; a22 = t;
     t = b1; b1 = b2; b2 = t;
   }
+  const double i11 = frcp(a11);
   {
-    const double m = a21 / a11;
+    const double m = a21 * i11;
     a22 = a22 - m * a12;
     b2 = b2 - m * b1;
   }
   x2 = b2 / a22;
-  x1 = (b1 - a12 * x2) / a11;
-  x0 = (b0 - a01 * x1 - a02 * x2) / a00;
+  x1 = (b1 - a12 * x2) * i11;
+  x0 = (b0 - a01 * x1 - a02 * x2) * i00;
 }
 
 __device__ inline void solve2(double a00, double a01, double a10, double a11, double b0, double b1,
@@ -560,11 +573,12 @@ __device__ inline void solve2(double a00, double a01, double a10, double a11, do
     t = a01; a01 = a11; a11 = t;
     t = b0; b0 = b1; b1 = t;
   }
-  const double m = a10 / a00;
+  const double i00 = frcp(a00);
+  const double m = a10 * i00;
   a11 = a11 - m * a01;
   b1 = b1 - m * b0;
   x1 = b1 / a11;
-  x0 = (b0 - a01 * x1) / a00;
+  x0 = (b0 - a01 * x1) * i00;
 }
 
 // ------------------------------------------------------------------ lane
@@ -767,16 +781,18 @@ __device__ inline void dust_linear(const Net& nt, const Par& pr, Lane& L, double
     const double b1 = h * double(d.Sir);
     const double E = L.Eir;
     double x0, x1, x2;
-    solve3(A00 * L.Td / s0, A01 * E / s0, A02 * Tg / s0,
-           A10 * L.Td / E, A11 * E / E, 0.0,
-           A20 * L.Td / s2, 0.0, A22 * Tg / s2,
-           b0 / s0, b1 / E, b2 / s2, x0, x1, x2);
+    const double i0 = frcp(s0), i1 = frcp(E), i2 = frcp(s2);
+    solve3(A00 * L.Td * i0, A01 * E * i0, A02 * Tg * i0,
+           A10 * L.Td * i1, A11, 0.0,
+           A20 * L.Td * i2, 0.0, A22 * Tg * i2,
+           b0 * i0, b1 * i1, b2 * i2, x0, x1, x2);
     L.Td = L.Td + x0 * L.Td;
     L.Eir = L.Eir + x1 * E;
     L.E = L.E + cv * (x2 * Tg);
   } else {
     double x0, x1;
-    solve2(A00 * L.Td / s0, A02 * Tg / s0, A20 * L.Td / s2, A22 * Tg / s2, b0 / s0, b2 / s2,
+    const double i0 = frcp(s0), i2 = frcp(s2);
+    solve2(A00 * L.Td * i0, A02 * Tg * i0, A20 * L.Td * i2, A22 * Tg * i2, b0 * i0, b2 * i2,
            x0, x1);
     L.Td = L.Td + x0 * L.Td;
     L.E = L.E + cv * (x1 * Tg);
@@ -822,8 +838,9 @@ __device__ bool subcycle(const Net& nt, const Par& pr, Lane& L) {
   const bool tight = dust_on && (L.rem * nu_dust / pr.f_chem >= double(pr.n_cyc));
   if (tight) L.fl |= F_TIGHT;
 
-  double nu = fmax(fabs(f0) / fmax(L.y2, pr.y_abs), fabs(f1) / fmax(L.ye, pr.y_abs));
-  if (!iso) nu = fmax(nu, fabs(fq + qgg) / Ek);
+  const double iEk = frcp(Ek);
+  double nu = fmax(fabs(f0) * frcp(fmax(L.y2, pr.y_abs)), fabs(f1) * frcp(fmax(L.ye, pr.y_abs)));
+  if (!iso) nu = fmax(nu, fabs(fq + qgg) * iEk);
   if (!tight) nu = fmax(nu, nu_dust);
 
   double h;
@@ -843,8 +860,9 @@ __device__ bool subcycle(const Net& nt, const Par& pr, Lane& L) {
 
   // chemistry + energy: (I - h J) du = h f, u = (y_H2, y_e, E/E_ref)
   {
-    const double dTy2 = iso ? 0.0 : T / ntr;
-    const double dTye = iso ? 0.0 : -(T / ntr);
+    const double Tn = T * frcp(ntr);
+    const double dTy2 = iso ? 0.0 : Tn;
+    const double dTye = iso ? 0.0 : -Tn;
     const double dTu = iso ? 0.0 : T;
     double J00 = double(ch.J[0][0]) + double(ch.J[0][2]) * dTy2;
     double J01 = double(ch.J[0][1]) + double(ch.J[0][2]) * dTye;
@@ -854,10 +872,10 @@ __device__ bool subcycle(const Net& nt, const Par& pr, Lane& L) {
     double J12 = double(ch.J[1][2]) * dTu;
     double J20 = 0.0, J21 = 0.0, J22 = 0.0, g2 = 0.0;
     if (!iso) {
-      g2 = fq / Ek;
-      J20 = (double(ch.J[2][0]) + double(ch.J[2][2]) * dTy2) / Ek;
-      J21 = (double(ch.J[2][1]) + double(ch.J[2][2]) * dTye) / Ek;
-      J22 = double(ch.J[2][2]) * dTu / Ek;
+      g2 = fq * iEk;
+      J20 = (double(ch.J[2][0]) + double(ch.J[2][2]) * dTy2) * iEk;
+      J21 = (double(ch.J[2][1]) + double(ch.J[2][2]) * dTye) * iEk;
+      J22 = double(ch.J[2][2]) * dTu * iEk;
     }
     double x0, x1, x2;
     solve3(1.0 - h * J00, -(h * J01), -(h * J02), -(h * J10), 1.0 - h * J11, -(h * J12),
@@ -1014,96 +1032,137 @@ __global__ __launch_bounds__(kBlock) void li_step_kernel(Args a) {
 }
 
 // ------------------------------------------------------------------ served
-// Claim up to `want` cells for one wave from the oldest published request
-// that still has unclaimed cells.  Executed by one lane.  The cursor packs
-// (request sequence << 32 | next cell) and only ever increases, so a
-// compare-and-swap on a stale value fails instead of claiming twice, and a
-// ring entry read through a stale cursor is never used.
+__device__ inline uint64_t sys_load(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// What a wave knows about the request it last claimed from and about the
+// published count; every lane holds the same copy.
+struct WaveCache {
+  uint64_t k = ~0ull;  // request sequence number of the cached entry
+  uint64_t pub = 0;    // published requests last seen
+  uint64_t n = 0, off = 0;
+  double dt = 0.0;
+};
+
 struct Claim {
   uint64_t seq, first, off;
   double dt;
   int take;
 };
 
-__device__ inline uint64_t sys_load(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-
-__device__ Claim claim_cells(const ServedArgs& a, int want) {
-  Claim c{0, 0, 0, 0.0, 0};
-  unsigned long long cur = __hip_atomic_load(a.claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  for (int attempt = 0; attempt < 64; ++attempt) {
-    const uint64_t k = cur >> 32, o = cur & 0xffffffffull;
-    const uint64_t pub =
-        __hip_atomic_load(a.published, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
-    if (k >= pub) return c;
-    const RingEntry* e = a.ring + (k % kRing);
-    const uint64_t n = sys_load(&e->n);
-    const uint64_t seq = sys_load(&e->seq);
-    if (seq != k || o >= n) {  // stale cursor: the entry was reused meanwhile
-      cur = __hip_atomic_load(a.claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      continue;
+// Claim up to `want` cells for one wave (executed by one lane).  Host
+// memory is read only when the published count or the request changes; the
+// cells themselves come from one atomicAdd on the request's slot counter,
+// so concurrent waves never retry.  A request found exhausted moves the
+// head on (compare-and-swap; a failure means another wave already did).
+__device__ Claim claim_cells(const ServedArgs& a, int want, WaveCache& c) {
+  Claim r{0, 0, 0, 0.0, 0};
+  uint64_t k = __hip_atomic_load(a.head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int attempt = 0; attempt < 16; ++attempt) {
+    if (k >= c.pub) {
+      c.pub = __hip_atomic_load(a.published, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+      if (k >= c.pub) return r;
     }
-    const uint64_t take = (n - o) < uint64_t(want) ? (n - o) : uint64_t(want);
-    const unsigned long long nxt = (o + take == n) ? ((k + 1) << 32) : (cur + take);
-    if (__hip_atomic_compare_exchange_strong(a.claim, &cur, nxt, __ATOMIC_RELAXED,
-                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-      c.seq = k;
-      c.first = o;
+    if (k != c.k) {
+      const RingEntry* e = a.ring + (k % kRing);
+      if (__hip_atomic_load(&e->seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) != k) {
+        k = __hip_atomic_load(a.head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        continue;
+      }
+      c.n = sys_load(&e->n);
       c.off = sys_load(&e->arena_off);
       c.dt = __longlong_as_double((long long)sys_load(reinterpret_cast<const uint64_t*>(&e->dt)));
-      c.take = int(take);
-      return c;
+      c.k = k;
     }
+    const uint32_t o = __hip_atomic_fetch_add(a.claimed + (k % kRing), uint32_t(want),
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (uint64_t(o) < c.n) {
+      const uint64_t left = c.n - o;
+      r.seq = k;
+      r.first = o;
+      r.off = c.off;
+      r.dt = c.dt;
+      r.take = int(left < uint64_t(want) ? left : uint64_t(want));
+      return r;
+    }
+    unsigned long long expect = k;
+    __hip_atomic_compare_exchange_strong(a.head, &expect, k + 1, __ATOMIC_RELAXED,
+                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    k = expect > k ? uint64_t(expect) : k + 1;
   }
-  return c;
+  return r;
 }
 
-// A lane has stored (or rejected) a cell of request `seq`: count it off; the
-// lane that stores the request's last cell reports completion to the host.
-__device__ inline void cell_done(const ServedArgs& a, uint64_t seq) {
-  const int slot = int(seq % kRing);
-  const int left = __hip_atomic_fetch_add(a.remaining + slot, -1, __ATOMIC_ACQ_REL,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-  if (left == 1)
-    __hip_atomic_store(a.done + slot, seq + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+// Count off the cells the wave's lanes have stored since the last flush:
+// one release fence for all of them, then one decrement per cell; the lane
+// that takes a request's count to zero raises its done word (system scope).
+// Wave-uniform call.
+__device__ inline void flush_done(const ServedArgs& a, uint64_t& pend) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  if (pend) {
+    const uint64_t seq = pend - 1;
+    const int slot = int(seq % kRing);
+    const int left = __hip_atomic_fetch_add(a.remaining + slot, -1, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+    if (left == 1) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __hip_atomic_store(a.done + slot, seq + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    pend = 0;
+  }
 }
 
 // Persistent drain: lanes refill from the request ring as they finish;
 // every cell is advanced by its own request's dt with the same per-lane
 // code as the plain step, so a cell's result does not depend on which
-// requests share the device with it.  A wave leaves once it has been idle
-// for idle_ticks with nothing to claim, or once its lifetime is over and
-// its lanes are done (each cell is bounded by n_sub_max subcycles).
+// requests share the device with it.  Idle waves back off (doubling waits)
+// and leave after idle_ticks without work; after life_ticks they stop
+// claiming and leave once their lanes are done (each cell is bounded by
+// n_sub_max subcycles), so every wave reaches an exit.
 template <class R>
 __global__ __launch_bounds__(kBlock) void served_drain_kernel(ServedArgs a) {
   const int lane = threadIdx.x & 63;
   int64_t cell = -1;
-  uint64_t seq = 0;
+  uint64_t seq = 0, pend = 0;
   Lane L;
+  WaveCache wc;
   const uint64_t t0 = (uint64_t)wall_clock64();
-  uint64_t next_try = t0, last_work = t0;
+  uint64_t next_try = t0, last_work = t0, backoff = a.backoff_ticks;
+  int since_flush = 0;
   bool closing = false;
   for (;;) {
     const unsigned long long idle = __ballot(cell < 0);
     const unsigned long long busy = __ballot(cell >= 0);
+    const bool pending = __ballot(pend != 0) != 0ull;
     const int nidle = __popcll(idle);
     const uint64_t now = (uint64_t)wall_clock64();
     if (now - t0 > a.life_ticks) closing = true;
+    if (pending && (busy == 0 || nidle >= a.refill_min || ++since_flush >= 64)) {
+      flush_done(a, pend);
+      since_flush = 0;
+    }
     if (!closing && nidle > 0 && (nidle >= a.refill_min || busy == 0) && now >= next_try) {
       const int leader = __ffsll((long long)idle) - 1;
       Claim c{0, 0, 0, 0.0, 0};
-      if (lane == leader) c = claim_cells(a, nidle);
+      if (lane == leader) c = claim_cells(a, nidle, wc);
+      wc.k = __shfl(wc.k, leader);
+      wc.pub = __shfl(wc.pub, leader);
+      wc.n = __shfl(wc.n, leader);
+      wc.off = __shfl(wc.off, leader);
+      wc.dt = __shfl(wc.dt, leader);
       const int take = __shfl(c.take, leader);
       if (take == 0) {
-        next_try = now + a.backoff_ticks;
+        next_try = now + backoff;
+        backoff = backoff * 2 < a.backoff_max_ticks ? backoff * 2 : a.backoff_max_ticks;
         if (busy == 0) {
           if (now - last_work > a.idle_ticks) break;
-          __builtin_amdgcn_s_sleep(32);
+          __builtin_amdgcn_s_sleep(64);
         }
         continue;
       }
       last_work = now;
+      backoff = a.backoff_ticks;
       const uint64_t cseq = __shfl(c.seq, leader);
       const uint64_t first = __shfl(c.first, leader);
       const uint64_t off = __shfl(c.off, leader);
@@ -1117,7 +1176,7 @@ __global__ __launch_bounds__(kBlock) void served_drain_kernel(ServedArgs a) {
           seq = cseq;
           if (!load_cell<R>(a.net, a.par, a.arena, cell, dt, L)) {
             cell = -1;
-            cell_done(a, seq);
+            pend = seq + 1;
           }
         }
       }
@@ -1125,17 +1184,18 @@ __global__ __launch_bounds__(kBlock) void served_drain_kernel(ServedArgs a) {
     }
     if (busy == 0) {
       if (closing || now - last_work > a.idle_ticks) break;
-      __builtin_amdgcn_s_sleep(32);
+      __builtin_amdgcn_s_sleep(64);
       continue;
     }
     if (cell >= 0) {
       if (subcycle<R>(fresh(a.netc), fresh(a.parc), L)) {
         store_cell<R>(a.net, a.par, a.arena, cell, L);
         cell = -1;
-        cell_done(a, seq);
+        pend = seq + 1;
       }
     }
   }
+  if (__ballot(pend != 0)) flush_done(a, pend);
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -1202,7 +1262,10 @@ __global__ __launch_bounds__(256) void order_scatter_kernel(const double* nh, in
 // Arena <-> caller copies of one request (grid-stride over its cells).
 __global__ __launch_bounds__(256) void copy_in_kernel(CopyArgs a) {
   const int64_t n = a.user.n;
-  if (blockIdx.x == 0 && threadIdx.x == 0 && a.remaining_slot) *a.remaining_slot = int32_t(n);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (a.remaining_slot) *a.remaining_slot = int32_t(n);
+    if (a.claimed_slot) *a.claimed_slot = 0u;
+  }
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x) {
     const int64_t j = a.off + i;

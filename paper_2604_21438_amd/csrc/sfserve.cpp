@@ -98,8 +98,9 @@ struct Queue {
   sfk::RingEntry* d_ring = nullptr;    // device views of the three above
   uint64_t* d_published = nullptr;
   uint64_t* d_done = nullptr;
-  unsigned long long* claim = nullptr; // device
-  int32_t* remaining = nullptr;        // device, kRing
+  unsigned long long* head = nullptr;  // device: oldest request with unclaimed cells
+  uint32_t* claimed = nullptr;         // device, kRing: cells handed out per slot
+  int32_t* remaining = nullptr;        // device, kRing: cells not yet stored per slot
   uint64_t next_seq = 0;
   std::deque<Req*> inflight;           // admitted, done not yet seen; seq order
   int64_t running = 0;                 // published, done not yet seen
@@ -184,6 +185,7 @@ sfk::CopyArgs copy_args(Server* s, const Req* r) {
   a.off = r->off;
   a.z_default = s->cfg.par.z_default;
   a.remaining_slot = s->q[r->prec].remaining + (r->seq % sfk::kRing);
+  a.claimed_slot = s->q[r->prec].claimed + (r->seq % sfk::kRing);
   a.ir_evolve = s->evolve ? 1 : 0;
   return a;
 }
@@ -362,7 +364,8 @@ void free_all(Server* s) {
     if (q.ring) (void)hipHostFree(q.ring);
     if (q.published) (void)hipHostFree(q.published);
     if (q.done) (void)hipHostFree(q.done);
-    if (q.claim) (void)hipFree(q.claim);
+    if (q.head) (void)hipFree(q.head);
+    if (q.claimed) (void)hipFree(q.claimed);
     if (q.remaining) (void)hipFree(q.remaining);
   }
   for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
@@ -467,10 +470,12 @@ Server* create(const Config& cfg, std::string* err, int* code) {
             hipSuccess ||
         hipHostGetDevicePointer(reinterpret_cast<void**>(&q.d_done), q.done, 0) != hipSuccess)
       return fail(s, SFC_E_DEVICE, "host pointer mapping");
-    if (hipMalloc(&q.claim, sizeof(unsigned long long)) != hipSuccess ||
+    if (hipMalloc(&q.head, sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc(&q.claimed, sizeof(uint32_t) * sfk::kRing) != hipSuccess ||
         hipMalloc(&q.remaining, sizeof(int32_t) * sfk::kRing) != hipSuccess)
       return fail(s, SFC_E_NOMEM, "served counters");
-    if (hipMemset(q.claim, 0, sizeof(unsigned long long)) != hipSuccess ||
+    if (hipMemset(q.head, 0, sizeof(unsigned long long)) != hipSuccess ||
+        hipMemset(q.claimed, 0, sizeof(uint32_t) * sfk::kRing) != hipSuccess ||
         hipMemset(q.remaining, 0, sizeof(int32_t) * sfk::kRing) != hipSuccess)
       return fail(s, SFC_E_DEVICE, "served counters");
 
@@ -480,12 +485,14 @@ Server* create(const Config& cfg, std::string* err, int* code) {
     a.arena = s->arena;
     a.ring = q.d_ring;
     a.published = q.d_published;
-    a.claim = q.claim;
+    a.head = q.head;
+    a.claimed = q.claimed;
     a.remaining = q.remaining;
     a.done = q.d_done;
-    a.idle_ticks = uint64_t(env_num("SFC_SERVE_IDLE_US", 2000.0) * 1e-6 * tps);
-    a.life_ticks = uint64_t(env_num("SFC_SERVE_LIFE_S", 30.0) * tps);
-    a.backoff_ticks = uint64_t(20e-6 * tps);
+    a.idle_ticks = uint64_t(env_num("SFC_SERVE_IDLE_MS", 100.0) * 1e-3 * tps);
+    a.life_ticks = uint64_t(env_num("SFC_SERVE_LIFE_S", 120.0) * tps);
+    a.backoff_ticks = uint64_t(10e-6 * tps);
+    a.backoff_max_ticks = uint64_t(500e-6 * tps);
     a.refill_min = cfg.refill_min;
     a.netc = cfg.netc;
     a.parc = cfg.parc;
