@@ -36,6 +36,25 @@ sys.path.insert(0, ROOT)
 FLOP_PER_SUBCYCLE = 1539.0
 PEAK_FP64_VALU = 78.6e12      # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 BYTES_PER_CELL = 132          # 8 float64 reads, 7 float64 writes, 3 int32 writes
+# HBM bytes of one binary64 launch on the 128^3 workload, from rocprofv3
+# --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what the
+# same counter reads for a 256 MiB device-to-device copy (bench.py
+# --calibrate-copy 256).  Valid only for the kernel source whose SHA-1 is
+# given: with any other source the figure is reported as null.
+TRAFFIC = {"kernel_sha1": None, "fetch_bytes": None, "write_bytes": None}
+KERNEL_SRC = os.path.join(ROOT, "paper_2604_21438_amd", "csrc", "sfk_li.hip")
+
+
+def kernel_sha1():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()
+
+
+def measured_traffic():
+    if TRAFFIC["kernel_sha1"] is None or TRAFFIC["kernel_sha1"] != kernel_sha1():
+        return None
+    return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
 STATE_KEYS = ("y_h2", "y_e", "eint", "tdust")
 
 
@@ -170,7 +189,7 @@ def main():
     ap.add_argument("--served-side", type=int, default=128)
     ap.add_argument("--served-budget-mib", type=int, default=8192)
     ap.add_argument("--served-load", type=float, default=0.8)
-    ap.add_argument("--cpu-cells", type=int, default=8192)
+    ap.add_argument("--cpu-cells", type=int, default=32768)
     ap.add_argument("--cells", type=int, default=None, help="fewer cells (testing only)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run three device-to-device copies of MIB MiB (a kernel of "
@@ -267,6 +286,7 @@ def main():
                         "log T ~ U[1,4], T_d = T, Z in {0.01,0.1,1}, dt = 10 kyr, "
                         "dust factor 1 (C_d = 1e4 erg/g/K), IR fixed",
             "cells": n, "dt_s": dt, "dust_factor": 1.0, "precision": "fp64",
+            "dispatch": "density",
         },
         "roofline": {
             "bound": "alu",
@@ -274,7 +294,9 @@ def main():
             "peak": PEAK_FP64_VALU / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_VALU,
-            "traffic": None,
+            "traffic": measured_traffic(),
+            "traffic_unit": "bytes per launch",
+            "algorithmic_bytes": n * BYTES_PER_CELL,
             "kernel": "li_step_kernel<double>",
             "flop_per_subcycle": FLOP_PER_SUBCYCLE,
             "subcycles_per_launch": d64["subcycles"],

@@ -151,7 +151,10 @@ enum {
   SFC_F_TIGHT = 1u << 1,   /* some subcycle used the implicit dust solve */
   SFC_F_NOCONV = 1u << 2,  /* that solve reached newton_max              */
   SFC_F_INVALID = 1u << 3, /* invalid input, cell unchanged              */
-  SFC_F_FLOOR = 1u << 4    /* a floor, clamp or rescale was applied      */
+  SFC_F_FLOOR = 1u << 4,   /* a floor, clamp or rescale was applied      */
+  SFC_F_NRFAIL = 1u << 5   /* NR comparator: a substep could not be made
+                              to converge (after 60 halvings or n_sub_max
+                              attempts); the cell keeps its last state    */
 };
 
 /* Advance every cell by dt_seconds (> 0, finite) on `hip_stream` (a
@@ -165,6 +168,20 @@ enum {
  * Errors: SFC_E_INVAL, SFC_E_DEVICE. */
 int sfc_chem_step(sfc_ctx* ctx, const sfc_cells* cells, double dt_seconds, int precision,
                   void* hip_stream);
+
+/* Fully implicit Newton-Raphson comparator (the paper's Sec. 2 scheme that
+ * the LI update replaces; validation and timing only): every cell is
+ * advanced over dt_seconds by backward-Euler substeps of (y_H2, y_e, T_g,
+ * T_d, E_IR), each solved by an outer Newton iteration on T_g (central
+ * difference, step 1e-4 T_g) around the dust/IR and chemistry groups,
+ * tolerance 1e-5 relaxed to 1e-3 after 10 outer iterations, 20 iterations
+ * per loop; a substep that fails is halved (Eq. substep_NRchem).  Binary64.
+ * Same buffers, ownership and asynchrony as sfc_chem_step; nsub receives
+ * the accepted substeps, niter the outer iterations, flags SFC_F_NRFAIL
+ * for a cell that could not finish.  C_d is the context's (the paper runs
+ * NR with the realistic value).
+ * Errors: SFC_E_INVAL, SFC_E_NOMEM, SFC_E_DEVICE. */
+int sfc_chem_step_nr(sfc_ctx* ctx, const sfc_cells* cells, double dt_seconds, void* hip_stream);
 
 /* ---- served form: continuous batching of AMR blocks ---- */
 

@@ -211,12 +211,14 @@ def li_step(cells: dict, dt: float, net: Network | None = None, params: Params |
 
 
 def nr_step(cells: dict, dt: float, net: Network | None = None, params: Params | None = None,
-            nthreads: int = 1) -> dict:
+            nthreads: int = 1, variant: str = "plain") -> dict:
+    """Newton-Raphson comparator over dt [s]; same variants as li_step."""
     net = net or default_network()
     params = params or default_params()
     out, n = _prepare(cells, params.ir_mode)
     c, keep = _cells(out, n)
-    rc = _lib().orc_nr_step(C.byref(net), C.byref(params), C.byref(c), float(dt), int(nthreads))
+    rc = _lib(variant=variant).orc_nr_step(C.byref(net), C.byref(params), C.byref(c), float(dt),
+                                            int(nthreads))
     if rc != 0:
         raise ValueError("orc_nr_step rejected its arguments")
     return out
@@ -301,7 +303,7 @@ def _rel(a, b, floor=1e-20):
 
 
 def rounding_spread(cells: dict, dt: float, ref: dict, net=None, params=None,
-                    nthreads: int = 1) -> np.ndarray:
+                    nthreads: int = 1, method: str = "li") -> np.ndarray:
     """Per cell, the largest relative change of any output between the
     reference result `ref` and three other valid roundings of the same
     computation: the contracted build with transcendentals nudged up, the
@@ -310,11 +312,12 @@ def rounding_spread(cells: dict, dt: float, ref: dict, net=None, params=None,
     energy moved by one unit in the last place.  A cell whose spread exceeds a
     tolerance is not determined to that tolerance by binary64 arithmetic."""
     params = params or default_params()
-    alt = [li_step(cells, dt, net, params, nthreads, variant="fma"),
-           li_step(cells, dt, net, params, nthreads, variant="dn")]
+    step = li_step if method == "li" else nr_step
+    alt = [step(cells, dt, net, params, nthreads, variant="fma"),
+           step(cells, dt, net, params, nthreads, variant="dn")]
     nudged = dict(cells)
     nudged["eint"] = np.nextafter(np.asarray(cells["eint"], np.float64), np.inf)
-    alt.append(li_step(nudged, dt, net, params, nthreads))
+    alt.append(step(nudged, dt, net, params, nthreads))
     spread = np.zeros(ref["nsub"].shape[0])
     for o in alt:
         for k in OUT_KEYS:

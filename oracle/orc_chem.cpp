@@ -1126,7 +1126,7 @@ static void nr_cell(const orc_network& net, const orc_params& p, const orc_cells
   /* substeps, Eq. substep_NRchem: first try the whole interval; on failure
    * i <- i+1, on success i <- max(i-1, 0); dt_sub = (dt - t_sub)/2^i. */
   real tsub = 0.0;
-  int lev = 0, nsub = 0, outer = 0;
+  int lev = 0, nsub = 0, outer = 0, attempts = 0;
   for (;;) {
     real dts = (dt - tsub) / std::ldexp(1.0, lev);
     State trial = s;
@@ -1142,6 +1142,11 @@ static void nr_cell(const orc_network& net, const orc_params& p, const orc_cells
         fl |= ORC_F_NRFAIL;
         break;
       }
+    }
+    /* Reading (no bound in the paper): at most n_sub_max substep attempts */
+    if (++attempts >= p.n_sub_max) {
+      fl |= ORC_F_NRFAIL;
+      break;
     }
   }
   store(net, p, cs, i, c, s, iso, Tiso, nsub, outer, fl);

@@ -21,7 +21,7 @@ DISPATCH_INDEX, DISPATCH_DENSITY = 0, 1
 IR_FIXED, IR_EVOLVE = 0, 1
 THERMAL_EVOLVE, THERMAL_ISOTHERMAL = 0, 1
 DUST_EVOLVE, DUST_FROZEN = 0, 1
-F_CAP, F_TIGHT, F_NOCONV, F_INVALID, F_FLOOR = 1, 2, 4, 8, 16
+F_CAP, F_TIGHT, F_NOCONV, F_INVALID, F_FLOOR, F_NRFAIL = 1, 2, 4, 8, 16, 32
 OK, E_INVAL, E_NOMEM, E_BUDGET, E_DEVICE, E_PENDING, E_VERSION, E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
 ABI_VERSION = 2
 NREAC, NPROC, NLINE = 12, 14, 5
@@ -73,7 +73,7 @@ class SfcResult(C.Structure):
 
 
 EXPORTS = ("sfc_network_default", "sfc_params_default", "sfc_chem_init", "sfc_chem_step",
-           "sfc_chem_submit", "sfc_chem_poll", "sfc_chem_drain", "sfc_chem_destroy",
+           "sfc_chem_step_nr", "sfc_chem_submit", "sfc_chem_poll", "sfc_chem_drain", "sfc_chem_destroy",
            "sfc_strerror", "sfc_last_error", "sfc_now")
 
 _LIB = None
@@ -98,6 +98,7 @@ def lib():
         L.sfc_chem_init.argtypes = [P(SfcNetwork), _d, _d, P(SfcParams), C.c_int, C.c_uint64,
                                     P(C.c_void_p)]
         L.sfc_chem_step.argtypes = [C.c_void_p, P(SfcCells), _d, C.c_int, C.c_void_p]
+        L.sfc_chem_step_nr.argtypes = [C.c_void_p, P(SfcCells), _d, C.c_void_p]
         L.sfc_chem_submit.argtypes = [C.c_void_p, P(SfcRequest), P(C.c_uint64)]
         L.sfc_chem_poll.argtypes = [C.c_void_p, C.c_uint64, P(SfcResult)]
         L.sfc_chem_drain.argtypes = [C.c_void_p]
@@ -107,7 +108,8 @@ def lib():
         L.sfc_last_error.argtypes = [C.c_void_p]
         L.sfc_last_error.restype = C.c_char_p
         L.sfc_now.restype = _d
-        for name in ("sfc_chem_init", "sfc_chem_step", "sfc_chem_submit", "sfc_chem_poll",
+        for name in ("sfc_chem_init", "sfc_chem_step", "sfc_chem_step_nr", "sfc_chem_submit",
+                     "sfc_chem_poll",
                      "sfc_chem_drain", "sfc_chem_destroy"):
             getattr(L, name).restype = C.c_int
         _LIB = L
@@ -234,6 +236,15 @@ class Context:
         sp = C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
         self._check(lib().sfc_chem_step(self._h, C.byref(c), float(dt), int(precision), sp),
                     "sfc_chem_step")
+
+    def step_nr(self, cells: dict, dt: float, stream=None) -> None:
+        """Advance the cells with the Newton-Raphson comparator (binary64)."""
+        import torch
+        c = make_cells(cells)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        sp = C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+        self._check(lib().sfc_chem_step_nr(self._h, C.byref(c), float(dt), sp), "sfc_chem_step_nr")
 
     def submit(self, cells: dict, dt: float, precision: int = MIXED, level: int = 0,
                tag: int = 0, sync: bool = True) -> int:

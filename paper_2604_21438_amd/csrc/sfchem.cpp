@@ -114,7 +114,7 @@ struct sfc_ctx {
   int64_t order_cap = 0;
   uint32_t* d_buckets = nullptr;
   int cus = 0;
-  int bpc[2] = {1, 1};
+  int bpc[3] = {1, 1, 1};  // blocks per CU: LI binary64, LI mixed, NR
   int refill_min = 1;
   std::string last_error;
   sfserve::Server* server = nullptr;
@@ -274,6 +274,7 @@ int sfc_chem_init(const sfc_network* net_in, double z_default, double dust_cap_f
   ctx->cus = prop.multiProcessorCount;
   ctx->bpc[0] = sfk::max_blocks_per_cu(0);
   ctx->bpc[1] = sfk::max_blocks_per_cu(1);
+  ctx->bpc[2] = sfk::max_blocks_per_cu(2);
   if (hipMalloc(&ctx->d_counter, sizeof(unsigned long long)) != hipSuccess) {
     delete ctx;
     return SFC_E_NOMEM;
@@ -315,14 +316,18 @@ int sfc_chem_init(const sfc_network* net_in, double z_default, double dust_cap_f
   return SFC_OK;
 }
 
-int sfc_chem_step(sfc_ctx* ctx, const sfc_cells* cells, double dt, int precision,
-                  void* hip_stream) {
+}  // extern "C"
+
+namespace {
+
+// Plain path launch; method 0 = LI binary64, 1 = LI mixed, 2 = NR binary64.
+int step_launch(sfc_ctx* ctx, const sfc_cells* cells, double dt, int method, void* hip_stream,
+                const char* who) {
   if (!ctx) return SFC_E_INVAL;
-  if (!cells_ok(ctx->par, cells)) return fail(ctx, SFC_E_INVAL, "sfc_chem_step: bad cell buffers");
+  if (!cells_ok(ctx->par, cells))
+    return fail(ctx, SFC_E_INVAL, std::string(who) + ": bad cell buffers");
   if (!(dt > 0.0) || !std::isfinite(dt))
-    return fail(ctx, SFC_E_INVAL, "sfc_chem_step: dt must be positive and finite");
-  if (precision != SFC_FP64 && precision != SFC_MIXED)
-    return fail(ctx, SFC_E_INVAL, "sfc_chem_step: unknown precision");
+    return fail(ctx, SFC_E_INVAL, std::string(who) + ": dt must be positive and finite");
   if (cells->n == 0) return SFC_OK;
   DeviceGuard g(ctx->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
@@ -336,9 +341,10 @@ int sfc_chem_step(sfc_ctx* ctx, const sfc_cells* cells, double dt, int precision
   a.netc = ctx->d_net;
   a.parc = ctx->d_par;
   const int64_t need = (cells->n + sfk::kBlock - 1) / sfk::kBlock;
-  const int64_t cap = int64_t(ctx->cus) * ctx->bpc[precision];
+  const int64_t cap = int64_t(ctx->cus) * ctx->bpc[method];
   const int grid = int(need < cap ? need : cap);
   a.order = nullptr;
+  a.dense = nullptr;
   // density dispatch pays off once lanes take several cells each
   if (ctx->dispatch == SFC_DISPATCH_DENSITY && cells->n > 2 * int64_t(grid) * sfk::kBlock &&
       cells->n < (int64_t(1) << 31)) {
@@ -351,17 +357,33 @@ int sfc_chem_step(sfc_ctx* ctx, const sfc_cells* cells, double dt, int precision
       ctx->order_cap = cells->n;
     }
     if (!ctx->d_buckets &&
-        hipMalloc(&ctx->d_buckets, 2 * sfk::kOrderBuckets * sizeof(uint32_t)) != hipSuccess)
+        hipMalloc(&ctx->d_buckets, sfk::kOrderWork * sizeof(uint32_t)) != hipSuccess)
       return fail(ctx, SFC_E_NOMEM, "sfc_chem_step: dispatch buckets");
     const hipError_t oe = sfk::launch_order(cells->nh, cells->n, ctx->d_order, ctx->d_buckets, s);
     if (oe != hipSuccess) return hip_fail(ctx, oe, "dispatch order launch");
     a.order = ctx->d_order;
+    a.dense = ctx->d_buckets + sfk::kOrderDenseWord;
   }
   hipError_t e = sfk::launch_reset(ctx->d_counter, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "reset launch");
-  e = sfk::launch_step(a, precision, grid, s);
+  e = method == 2 ? sfk::launch_step_nr(a, grid, s) : sfk::launch_step(a, method, grid, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "step launch");
   return SFC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sfc_chem_step(sfc_ctx* ctx, const sfc_cells* cells, double dt, int precision,
+                  void* hip_stream) {
+  if (ctx && precision != SFC_FP64 && precision != SFC_MIXED)
+    return fail(ctx, SFC_E_INVAL, "sfc_chem_step: unknown precision");
+  return step_launch(ctx, cells, dt, precision, hip_stream, "sfc_chem_step");
+}
+
+int sfc_chem_step_nr(sfc_ctx* ctx, const sfc_cells* cells, double dt, void* hip_stream) {
+  return step_launch(ctx, cells, dt, 2, hip_stream, "sfc_chem_step_nr");
 }
 
 int sfc_chem_submit(sfc_ctx* ctx, const sfc_request* req, uint64_t* ticket) {

@@ -56,6 +56,7 @@ struct Args {
   const Net* netc;              // device copies of net and par (read-only)
   const Par* parc;
   const int32_t* order;         // lane work item -> cell (null: identity)
+  const uint32_t* dense;        // length of the density-ordered head of order (null: 0)
 };
 
 // Served form.  Requests are published by the host into a ring that lives
@@ -105,15 +106,20 @@ struct CopyArgs {
 
 // host-callable launchers (defined in sfk_li.hip)
 hipError_t launch_step(const Args& a, int precision, int grid, hipStream_t s);
+hipError_t launch_step_nr(const Args& a, int grid, hipStream_t s);  // binary64 NR comparator
 hipError_t launch_reset(unsigned long long* counter, hipStream_t s);
-int max_blocks_per_cu(int precision);
+int max_blocks_per_cu(int precision);  // 0 LI binary64, 1 LI mixed, 2 NR
 int served_blocks_per_cu(int precision);
 hipError_t launch_served(const ServedArgs& a, int precision, int grid, hipStream_t s);
 hipError_t launch_copy_in(const CopyArgs& a, hipStream_t s);
 hipError_t launch_copy_out(const CopyArgs& a, hipStream_t s);
-// Density dispatch: order[0..n) = cells by decreasing half-octave of n_H
-// (counting sort; work holds 2 * kOrderBuckets counters, n < 2^31).
+// Density dispatch: order[0..n) = the densest quarter of the cells by
+// decreasing half-octave of n_H, then the rest in index order (n < 2^31;
+// work holds kOrderWork uint32 counters).
 constexpr int kOrderBuckets = 128;
+constexpr int kOrderBlocks = 1024;
+constexpr int kOrderWork = 2 * kOrderBuckets + 4 + 2 * kOrderBlocks;
+constexpr int kOrderDenseWord = 2 * kOrderBuckets + 1;  // plan[1]: length of the dense head
 hipError_t launch_order(const double* nh, int64_t n, int32_t* order, uint32_t* work,
                         hipStream_t s);
 

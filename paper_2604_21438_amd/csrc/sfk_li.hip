@@ -897,6 +897,199 @@ __device__ bool subcycle(const Net& nt, const Par& pr, Lane& L) {
   return last;
 }
 
+// ------------------------------------------------------------------ NR
+// Fully implicit Newton-Raphson comparator (Sec. 2, the iterative scheme
+// the LI method replaces; binary64 only).  Backward Euler over a substep
+// dts for (y_H2, y_e, T_g, T_d, E_IR), solved as three nested groups: the
+// outer Newton iteration on T_g (derivative of the energy residual by a
+// central difference, step 1e-4 T_g), and at each trial T_g the dust/IR
+// group and then the chemistry group.  Tolerance 1e-5 relative, relaxed to
+// 1e-3 after half of the 20 allowed outer iterations; every loop gives up
+// after 20 iterations, and a failed substep is halved (Eq. substep_NRchem).
+// Energies are carried per k_B n_H [K], as in the LI kernel.
+struct NRState {
+  double y2, ye, T, Td, Eir;
+};
+
+// group (ii): (T_d, E_IR) at fixed T_g
+__device__ inline bool nr_dust(const Net& nt, const Par& pr, const CellK& ck, double Td0,
+                               double Eir0, double dts, double T, double tol, double& Td,
+                               double& Eir, int32_t& its) {
+  const double ctil = pr.c_red * CL;
+  const double ac = ARAD * CL;
+  for (int it = 1; it <= 20; ++it) {
+    ++its;
+    Dust<double> d;
+    dust_eval<double>(nt, pr, T, Td, Eir, ck, d);
+    const double td3 = Td * Td * Td;
+    const double F1 = pr.cd * (Td - Td0) - dts * d.Sd;
+    const double J11 = pr.cd + dts * (ac * td3 * d.betad + d.G * d.gd);
+    double dTd, dE = 0.0;
+    if (pr.ir_mode == 1) {
+      const double F2 = Eir - Eir0 - dts * d.Sir;
+      const double J12 = -(dts * ctil * d.betair);
+      const double J21 = -(dts * ck.rho * ck.fd * ac * td3 * d.betad);
+      const double J22 = 1.0 + dts * ck.rho * ck.fd * ctil * d.betair;
+      const double det = J11 * J22 - J12 * J21;
+      dTd = -(F1 * J22 - J12 * F2) / det;
+      dE = -(J11 * F2 - J21 * F1) / det;
+    } else {
+      dTd = -F1 / J11;
+    }
+    double Tn = Td + dTd;
+    bool ok = fabs(dTd) <= tol * fabs(Tn);
+    if (Tn < 0.5 * Td) { Tn = 0.5 * Td; ok = false; }
+    if (Tn > 2.0 * Td) { Tn = 2.0 * Td; ok = false; }
+    double En = Eir;
+    if (pr.ir_mode == 1) {
+      En = Eir + dE;
+      ok = ok && fabs(dE) <= tol * fabs(En);
+      if (En < 0.5 * Eir) { En = 0.5 * Eir; ok = false; }
+      if (En > 2.0 * Eir) { En = 2.0 * Eir; ok = false; }
+    }
+    Td = Tn;
+    Eir = En;
+    if (ok) return true;
+  }
+  return false;
+}
+
+// group (iii): (y_H2, y_e) at fixed T_g, T_d; steps that would leave the
+// bounds are damped towards them
+__device__ inline bool nr_chem(const Net& nt, const Par& pr, const CellK& ck, double y20,
+                               double ye0, double dts, double T, double Td, double tol,
+                               double& y2, double& ye, int32_t& its) {
+  for (int it = 1; it <= 20; ++it) {
+    ++its;
+    Chem<double> ch;
+    assemble<double>(nt, pr, y2, ye, Td, T, ck, ch);
+    const double F1 = y2 - y20 - dts * ch.f[0];
+    const double F2 = ye - ye0 - dts * ch.f[1];
+    const double J11 = 1.0 - dts * ch.J[0][0], J12 = -(dts * ch.J[0][1]);
+    const double J21 = -(dts * ch.J[1][0]), J22 = 1.0 - dts * ch.J[1][1];
+    const double det = J11 * J22 - J12 * J21;
+    const double d1 = -(F1 * J22 - J12 * F2) / det;
+    const double d2 = -(J11 * F2 - J21 * F1) / det;
+    double n1 = y2 + d1, n2 = ye + d2;
+    bool ok = fabs(d1) <= tol * fmax(fabs(n1), pr.y_abs) &&
+              fabs(d2) <= tol * fmax(fabs(n2), pr.y_abs);
+    if (n1 < 0.0) { n1 = 0.1 * y2; ok = false; }
+    if (n1 > 0.5) { n1 = 0.5 * (y2 + 0.5); ok = false; }
+    if (n2 < 0.0) { n2 = 0.1 * ye; ok = false; }
+    if (n2 > 1.0) { n2 = 0.5 * (ye + 1.0); ok = false; }
+    y2 = n1;
+    ye = n2;
+    if (ok) return true;
+  }
+  return false;
+}
+
+// inner groups at trial T; G = residual of the gas energy equation / (k_B n)
+__device__ inline bool nr_inner(const Net& nt, const Par& pr, const CellK& ck, const Lane& s0,
+                                double dts, double T, double tol, bool dust_on, NRState& g,
+                                double& G, int32_t& its) {
+  if (dust_on && !nr_dust(nt, pr, ck, s0.Td, s0.Eir, dts, T, tol, g.Td, g.Eir, its)) return false;
+  if (!nr_chem(nt, pr, ck, s0.y2, s0.ye, dts, T, g.Td, tol, g.y2, g.ye, its)) return false;
+  Chem<double> ch;
+  assemble<double>(nt, pr, g.y2, g.ye, g.Td, T, ck, ch);
+  const double knb = KB * ck.n;
+  double gas_grain = 0.0;
+  if (dust_on) {
+    Dust<double> d;
+    dust_eval<double>(nt, pr, T, g.Td, g.Eir, ck, d);
+    gas_grain = d.Sg * (ck.rho / knb);
+  }
+  G = cvk(pr, g.y2, g.ye) * T - s0.E / knb - dts * (ch.f[2] + gas_grain);
+  return true;
+}
+
+// One backward-Euler substep of length dts from L; on success L holds the
+// new state.  Outer iterations are counted in L.nit.
+__device__ bool nr_substep(const Net& nt, const Par& pr, Lane& L, double dts) {
+  const bool iso = pr.thermal_mode == 1;
+  const bool dust_on = (pr.dust_mode == 0) && !iso;
+  const double knb = KB * L.ck.n;
+  const Lane s0 = L;
+  NRState g{L.y2, L.ye, iso ? L.Tiso : L.E / (knb * cvk(pr, L.y2, L.ye)), L.Td, L.Eir};
+  int32_t its = 0;
+  if (iso) {
+    double Gv;
+    if (!nr_inner(nt, pr, L.ck, s0, dts, L.Tiso, 1e-5, dust_on, g, Gv, its)) return false;
+    L.y2 = g.y2;
+    L.ye = g.ye;
+    L.Td = g.Td;
+    L.Eir = g.Eir;
+    L.E = knb * cvk(pr, L.y2, L.ye) * L.Tiso;
+    L.nit += 1;
+    return true;
+  }
+  double tol = 1e-5;
+  for (int it = 1; it <= 20; ++it) {
+    L.nit += 1;
+    if (it > 10) tol = 1e-3;
+    const double T = g.T;
+    const double dl = 1e-4 * T;
+    NRState gm = g, gc = g, gp = g;
+    double Gm, Gc, Gp;
+    if (!nr_inner(nt, pr, L.ck, s0, dts, T - dl, tol, dust_on, gm, Gm, its)) return false;
+    if (!nr_inner(nt, pr, L.ck, s0, dts, T, tol, dust_on, gc, Gc, its)) return false;
+    if (!nr_inner(nt, pr, L.ck, s0, dts, T + dl, tol, dust_on, gp, Gp, its)) return false;
+    const double dG = (Gp - Gm) / (2.0 * dl);
+    double Tn = T - Gc / dG;
+    bool limited = false;
+    if (!(Tn > 0.5 * T)) { Tn = 0.5 * T; limited = true; }
+    if (!(Tn < 2.0 * T)) { Tn = 2.0 * T; limited = true; }
+    if (Tn < pr.t_cmb) { Tn = pr.t_cmb; limited = true; }
+    const bool ok = !limited && fabs(Tn - T) <= tol * Tn &&
+                    fabs(gc.y2 - g.y2) <= tol * fmax(gc.y2, pr.y_abs) &&
+                    fabs(gc.ye - g.ye) <= tol * fmax(gc.ye, pr.y_abs) &&
+                    fabs(gc.Td - g.Td) <= tol * gc.Td;
+    g = gc;
+    g.T = Tn;
+    if (ok) {
+      double Gv;
+      if (!nr_inner(nt, pr, L.ck, s0, dts, Tn, tol, dust_on, g, Gv, its)) return false;
+      L.y2 = g.y2;
+      L.ye = g.ye;
+      L.Td = g.Td;
+      L.Eir = g.Eir;
+      L.E = knb * cvk(pr, L.y2, L.ye) * Tn;
+      return true;
+    }
+  }
+  return false;
+}
+
+constexpr uint32_t F_NRFAIL = 32u;
+
+// One substep attempt of the NR driver (Eq. substep_NRchem): the first
+// try covers the whole interval; dts = (dt - t_sub) / 2^lev, lev + 1 on
+// failure, max(lev - 1, 0) on success.  L.rem holds dt, tsub and lev the
+// driver state.  At most n_sub_max attempts (then NRFAIL), so every cell
+// ends.  Returns true when the cell is done.
+__device__ bool nr_attempt(const Net& nt, const Par& pr, Lane& L, double& tsub, int& lev,
+                           int& attempts) {
+  const double dts = (L.rem - tsub) / ldexp(1.0, lev);
+  Lane trial = L;
+  const bool ok = nr_substep(nt, pr, trial, dts);
+  L.nit = trial.nit;
+  ++attempts;
+  if (ok) {
+    const int32_t nit = L.nit;
+    L = trial;
+    L.nit = nit;
+    L.nsub += 1;
+    if (lev == 0) return true;
+    tsub = tsub + dts;
+    lev = lev > 0 ? lev - 1 : 0;
+  } else {
+    ++lev;
+    if (lev > 60) { L.fl |= F_NRFAIL; return true; }
+  }
+  if (attempts >= pr.n_sub_max) { L.fl |= F_NRFAIL; return true; }
+  return false;
+}
+
 // ------------------------------------------------------------------ I/O
 // Load a cell; returns false (and writes the invalid marker) on bad input.
 template <class R>
@@ -991,45 +1184,94 @@ __device__ inline const Par& fresh(const Par* p) {
   return *(const Par*)q;
 }
 
+// The kernel's own argument block, re-read (scalar loads) wherever it is
+// used inside the cell loop instead of being held in SGPRs across it: the
+// ~40 pointers and scalars it holds would otherwise spill to VGPR lanes.
+template <class A>
+__device__ inline const A& kargs() {
+  typedef const __attribute__((address_space(4))) A CA;
+  CA* p = (CA*)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(p));
+  return *(const A*)p;
+}
+
 // ------------------------------------------------------------------ kernels
 // Persistent lane-refill driver.  cell: >= 0 working, -1 idle, -2 retired
 // (the counter passed the end).  Every lane either works on a cell, whose
 // subcycles are bounded by n_sub_max, or retires; the wave leaves once all
 // its lanes have retired.
-template <class R>
-__global__ __launch_bounds__(kBlock) void li_step_kernel(Args a) {
+// Past the density-ordered head, work positions are claimed 64 at a time
+// per wave (one atomicAdd) into a wave-local stash that idle lanes draw
+// from in order: the cells behind 64 consecutive positions (four cache
+// lines per array in index order) are then all read and written through
+// the L2 of the XCD the wave runs on.
+constexpr unsigned kStash = 64;
+
+// kNR selects the Newton-Raphson comparator instead of the LI subcycle
+// (binary64 only); both share the lane refill, stash and dispatch.
+template <class R, bool kNR>
+__global__ __launch_bounds__(kBlock) void li_step_kernel(Args) {
   const int lane = threadIdx.x & 63;
   int64_t cell = -1;
   Lane L;
+  double tsub = 0.0;  // NR driver state
+  int lev = 0, attempts = 0;
+  unsigned long long sbase = 0;  // wave-uniform stash: positions [sbase, sbase + sleft)
+  unsigned sleft = 0;
   for (;;) {
+    const Args& a = kargs<Args>();
     const unsigned long long idle = __ballot(cell == -1);
     const unsigned long long busy = __ballot(cell >= 0);
     const int nidle = __popcll(idle);
     if (nidle > 0 && (nidle >= a.refill_min || busy == 0)) {
-      const int leader = __ffsll((long long)idle) - 1;
-      unsigned long long base = 0;
-      if (lane == leader) base = atomicAdd(a.counter, (unsigned long long)nidle);
-      base = __shfl(base, leader);
+      if (sleft == 0) {
+        // inside the density-ordered head claim only what the idle lanes
+        // take now (those cells are long and must not wait in a stash)
+        const int leader = __ffsll((long long)idle) - 1;
+        unsigned long long base = 0;
+        unsigned want = kStash;
+        if (lane == leader) {
+          const unsigned long long head = a.dense ? (unsigned long long)(*a.dense) : 0ull;
+          if (__hip_atomic_load(a.counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < head)
+            want = unsigned(nidle);
+          base = atomicAdd(a.counter, (unsigned long long)want);
+        }
+        sbase = __shfl(base, leader);
+        sleft = unsigned(__shfl(int(want), leader));
+      }
+      const unsigned take = unsigned(nidle) < sleft ? unsigned(nidle) : sleft;
       if (cell == -1) {
-        const unsigned long long idx = base + lanes_below(idle);
-        if (idx < (unsigned long long)a.c.n) {
-          cell = a.order ? int64_t(a.order[idx]) : int64_t(idx);
-          if (!load_cell<R>(a.net, a.par, a.c, cell, a.dt, L)) cell = -1;
-        } else {
-          cell = -2;
+        const unsigned r = lanes_below(idle);
+        if (r < take) {
+          const unsigned long long idx = sbase + r;
+          if (idx < (unsigned long long)a.c.n) {
+            cell = a.order ? int64_t(a.order[idx]) : int64_t(idx);
+            if (!load_cell<R>(fresh(a.netc), fresh(a.parc), a.c, cell, a.dt, L)) cell = -1;
+            tsub = 0.0;
+            lev = 0;
+            attempts = 0;
+          } else {
+            cell = -2;
+          }
         }
       }
+      sbase += take;
+      sleft -= take;
       continue;
     }
     if (busy == 0) break;
     if (cell >= 0) {
-      if (subcycle<R>(fresh(a.netc), fresh(a.parc), L)) {
-        store_cell<R>(a.net, a.par, a.c, cell, L);
+      const bool done = kNR ? nr_attempt(fresh(a.netc), fresh(a.parc), L, tsub, lev, attempts)
+                            : subcycle<R>(fresh(a.netc), fresh(a.parc), L);
+      if (done) {
+        store_cell<R>(fresh(a.netc), fresh(a.parc), a.c, cell, L);
         cell = -1;
       }
     }
   }
 }
+
+__global__ void reset_kernel(unsigned long long* counter) { *counter = 0ull; }
 
 // ------------------------------------------------------------------ served
 __device__ inline uint64_t sys_load(const uint64_t* p) {
@@ -1121,17 +1363,18 @@ __device__ inline void flush_done(const ServedArgs& a, uint64_t& pend) {
 // claiming and leave once their lanes are done (each cell is bounded by
 // n_sub_max subcycles), so every wave reaches an exit.
 template <class R>
-__global__ __launch_bounds__(kBlock) void served_drain_kernel(ServedArgs a) {
+__global__ __launch_bounds__(kBlock) void served_drain_kernel(ServedArgs) {
   const int lane = threadIdx.x & 63;
   int64_t cell = -1;
   uint64_t seq = 0, pend = 0;
   Lane L;
   WaveCache wc;
   const uint64_t t0 = (uint64_t)wall_clock64();
-  uint64_t next_try = t0, last_work = t0, backoff = a.backoff_ticks;
+  uint64_t next_try = t0, last_work = t0, backoff = kargs<ServedArgs>().backoff_ticks;
   int since_flush = 0;
   bool closing = false;
   for (;;) {
+    const ServedArgs& a = kargs<ServedArgs>();
     const unsigned long long idle = __ballot(cell < 0);
     const unsigned long long busy = __ballot(cell >= 0);
     const bool pending = __ballot(pend != 0) != 0ull;
@@ -1174,7 +1417,7 @@ __global__ __launch_bounds__(kBlock) void served_drain_kernel(ServedArgs a) {
         if (r < unsigned(take)) {
           cell = int64_t(off + first + r);
           seq = cseq;
-          if (!load_cell<R>(a.net, a.par, a.arena, cell, dt, L)) {
+          if (!load_cell<R>(fresh(a.netc), fresh(a.parc), a.arena, cell, dt, L)) {
             cell = -1;
             pend = seq + 1;
           }
@@ -1189,18 +1432,23 @@ __global__ __launch_bounds__(kBlock) void served_drain_kernel(ServedArgs a) {
     }
     if (cell >= 0) {
       if (subcycle<R>(fresh(a.netc), fresh(a.parc), L)) {
-        store_cell<R>(a.net, a.par, a.arena, cell, L);
+        store_cell<R>(fresh(a.netc), fresh(a.parc), a.arena, cell, L);
         cell = -1;
         pend = seq + 1;
       }
     }
   }
-  if (__ballot(pend != 0)) flush_done(a, pend);
+  if (__ballot(pend != 0)) flush_done(kargs<ServedArgs>(), pend);
 }
 
 // ------------------------------------------------------------------ dispatch
-// Counting sort of the cells by half-octave of n_H, densest first.  Invalid
-// densities (non-positive, NaN) go to the last bucket.
+// Density dispatch.  The densest cells (those in the top half-octave
+// buckets of n_H that together hold at most a quarter of the cells) go
+// first, bucket by bucket, densest first; all other cells follow in index
+// order, so that most lanes still read consecutive cells.  Each block owns
+// one contiguous chunk of cells.  Invalid densities (non-positive, NaN) go
+// to the lowest bucket.  Work buffer (uint32): hist[B] | offs[B] | plan[4]
+// | blockcnt[kOrderBlocks] | blockoff[kOrderBlocks].
 __device__ inline int density_bucket(double nh) {
   if (!(nh > 0.0) || !(nh < 1.0e300)) return 0;
   const float l2 = __builtin_amdgcn_logf(float(nh));  // log2, binary32 is plenty
@@ -1209,53 +1457,134 @@ __device__ inline int density_bucket(double nh) {
 }
 
 __global__ __launch_bounds__(256) void order_zero_kernel(uint32_t* work) {
-  for (int t = threadIdx.x; t < 2 * kOrderBuckets; t += blockDim.x) work[t] = 0u;
+  for (int t = threadIdx.x; t < kOrderBuckets; t += blockDim.x) work[t] = 0u;
+}
+
+struct OrderWork {
+  uint32_t *hist, *offs, *plan, *blockcnt, *blockoff;
+};
+__device__ inline OrderWork order_work(uint32_t* w) {
+  return {w, w + kOrderBuckets, w + 2 * kOrderBuckets, w + 2 * kOrderBuckets + 4,
+          w + 2 * kOrderBuckets + 4 + kOrderBlocks};
+}
+// [begin, end) of block b's chunk (chunk is a multiple of 256)
+__device__ inline void chunk_of(int64_t n, int64_t chunk, int b, int64_t& begin, int64_t& end) {
+  begin = int64_t(b) * chunk;
+  end = begin + chunk < n ? begin + chunk : n;
 }
 
 __global__ __launch_bounds__(256) void order_count_kernel(const double* nh, int64_t n,
-                                                          uint32_t* hist) {
+                                                          int64_t chunk, uint32_t* work) {
   __shared__ uint32_t h[kOrderBuckets];
   for (int t = threadIdx.x; t < kOrderBuckets; t += blockDim.x) h[t] = 0u;
   __syncthreads();
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * blockDim.x)
+  int64_t begin, end;
+  chunk_of(n, chunk, blockIdx.x, begin, end);
+  for (int64_t i = begin + threadIdx.x; i < end; i += blockDim.x)
     atomicAdd(&h[density_bucket(nh[i])], 1u);
   __syncthreads();
+  const OrderWork w = order_work(work);
   for (int t = threadIdx.x; t < kOrderBuckets; t += blockDim.x)
-    if (h[t]) atomicAdd(&hist[t], h[t]);
+    if (h[t]) atomicAdd(&w.hist[t], h[t]);
 }
 
-// offs[b] = number of cells in buckets above b (one thread; 128 entries)
-__global__ void order_scan_kernel(const uint32_t* hist, uint32_t* offs) {
+// One thread: the cut bucket, the dense buckets' offsets (densest first)
+// and the number of dense cells.
+__global__ void order_plan_kernel(int64_t n, uint32_t* work) {
   if (threadIdx.x != 0) return;
-  uint32_t sum = 0u;
+  const OrderWork w = order_work(work);
+  const uint64_t cap = uint64_t(n) / 4;
+  uint64_t sum = 0;
+  int cut = kOrderBuckets;
   for (int b = kOrderBuckets - 1; b >= 0; --b) {
-    offs[b] = sum;
-    sum += hist[b];
+    if (sum + w.hist[b] > cap) break;
+    sum += w.hist[b];
+    cut = b;
+  }
+  uint32_t off = 0u;
+  for (int b = kOrderBuckets - 1; b >= 0; --b) {
+    w.offs[b] = b >= cut ? off : 0u;
+    if (b >= cut) off += w.hist[b];
+  }
+  w.plan[0] = uint32_t(cut);
+  w.plan[1] = off;
+}
+
+__global__ __launch_bounds__(256) void order_blockcount_kernel(const double* nh, int64_t n,
+                                                               int64_t chunk, uint32_t* work) {
+  __shared__ uint32_t c;
+  if (threadIdx.x == 0) c = 0u;
+  __syncthreads();
+  const OrderWork w = order_work(work);
+  const int cut = int(w.plan[0]);
+  int64_t begin, end;
+  chunk_of(n, chunk, blockIdx.x, begin, end);
+  uint32_t mine = 0u;
+  for (int64_t i = begin + threadIdx.x; i < end; i += blockDim.x)
+    mine += density_bucket(nh[i]) < cut ? 1u : 0u;
+  atomicAdd(&c, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) w.blockcnt[blockIdx.x] = c;
+}
+
+// One thread: where each block's index-ordered cells start.
+__global__ void order_blockscan_kernel(int nblocks, uint32_t* work) {
+  if (threadIdx.x != 0) return;
+  const OrderWork w = order_work(work);
+  uint32_t off = w.plan[1];
+  for (int b = 0; b < nblocks; ++b) {
+    w.blockoff[b] = off;
+    off += w.blockcnt[b];
   }
 }
 
-// Each block reserves one range per bucket for its own cells (same
-// grid-stride set as the count), then places them.
+// Dense cells take a range reserved per bucket (any order inside a bucket);
+// the others are placed in index order: the chunk is walked in tiles of
+// 256, each wave ranks its lanes with a ballot and the waves stack up in
+// order.
 __global__ __launch_bounds__(256) void order_scatter_kernel(const double* nh, int64_t n,
-                                                            uint32_t* offs, int32_t* order) {
+                                                            int64_t chunk, uint32_t* work,
+                                                            int32_t* order) {
   __shared__ uint32_t cnt[kOrderBuckets], base[kOrderBuckets];
+  __shared__ uint32_t wtot[4];
+  __shared__ uint32_t running;
+  const OrderWork w = order_work(work);
+  const int cut = int(w.plan[0]);
+  int64_t begin, end;
+  chunk_of(n, chunk, blockIdx.x, begin, end);
   for (int t = threadIdx.x; t < kOrderBuckets; t += blockDim.x) cnt[t] = 0u;
+  if (threadIdx.x == 0) running = 0u;
   __syncthreads();
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * blockDim.x)
-    atomicAdd(&cnt[density_bucket(nh[i])], 1u);
+  for (int64_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
+    const int b = density_bucket(nh[i]);
+    if (b >= cut) atomicAdd(&cnt[b], 1u);
+  }
   __syncthreads();
   for (int t = threadIdx.x; t < kOrderBuckets; t += blockDim.x) {
-    base[t] = cnt[t] ? atomicAdd(&offs[t], cnt[t]) : 0u;
+    base[t] = cnt[t] ? atomicAdd(&w.offs[t], cnt[t]) : 0u;
     cnt[t] = 0u;
   }
   __syncthreads();
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * blockDim.x) {
-    const int b = density_bucket(nh[i]);
-    const uint32_t r = atomicAdd(&cnt[b], 1u);
-    order[base[b] + r] = int32_t(i);
+  const int wave = threadIdx.x >> 6;
+  const uint32_t boff = w.blockoff[blockIdx.x];
+  for (int64_t t0 = begin; t0 < end; t0 += blockDim.x) {
+    const int64_t i = t0 + threadIdx.x;
+    const int b = i < end ? density_bucket(nh[i]) : kOrderBuckets;
+    const bool rest = i < end && b < cut;
+    const unsigned long long m = __ballot(rest);
+    const uint32_t rank = lanes_below(m);
+    if ((threadIdx.x & 63) == 0) wtot[wave] = uint32_t(__popcll(m));
+    __syncthreads();
+    uint32_t before = running;
+    for (int v = 0; v < wave; ++v) before += wtot[v];
+    if (rest) order[boff + before + rank] = int32_t(i);
+    if (i < end && b >= cut) {
+      const uint32_t r = atomicAdd(&cnt[b], 1u);
+      order[base[b] + r] = int32_t(i);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) running += wtot[0] + wtot[1] + wtot[2] + wtot[3];
+    __syncthreads();
   }
 }
 
@@ -1301,15 +1630,20 @@ __global__ __launch_bounds__(256) void copy_out_kernel(CopyArgs a) {
   }
 }
 
-__global__ void reset_kernel(unsigned long long* counter) { *counter = 0ull; }
+
 
 }  // namespace
 
 hipError_t launch_step(const Args& a, int precision, int grid, hipStream_t s) {
   if (precision == 1)
-    hipLaunchKernelGGL(li_step_kernel<float>, dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((li_step_kernel<float, false>), dim3(grid), dim3(kBlock), 0, s, a);
   else
-    hipLaunchKernelGGL(li_step_kernel<double>, dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((li_step_kernel<double, false>), dim3(grid), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_nr(const Args& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((li_step_kernel<double, true>), dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
@@ -1320,10 +1654,15 @@ hipError_t launch_reset(unsigned long long* counter, hipStream_t s) {
 
 int max_blocks_per_cu(int precision) {
   int nb = 0;
-  if (precision == 1)
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, li_step_kernel<float>, kBlock, 0);
+  if (precision == 2)
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, li_step_kernel<double, true>, kBlock,
+                                                       0);
+  else if (precision == 1)
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, li_step_kernel<float, false>, kBlock,
+                                                       0);
   else
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, li_step_kernel<double>, kBlock, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, li_step_kernel<double, false>, kBlock,
+                                                       0);
   return nb > 0 ? nb : 1;
 }
 
@@ -1353,13 +1692,16 @@ int copy_grid(int64_t n) {
 
 hipError_t launch_order(const double* nh, int64_t n, int32_t* order, uint32_t* work,
                         hipStream_t s) {
-  const int64_t g = (n + 255) / 256;
-  const int grid = int(g < 1024 ? (g > 0 ? g : 1) : 1024);
+  const int64_t tiles = (n + 255) / 256;
+  const int grid = int(tiles < kOrderBlocks ? (tiles > 0 ? tiles : 1) : kOrderBlocks);
+  const int64_t chunk = ((tiles + grid - 1) / grid) * 256;
   hipLaunchKernelGGL(order_zero_kernel, dim3(1), dim3(256), 0, s, work);
-  hipLaunchKernelGGL(order_count_kernel, dim3(grid), dim3(256), 0, s, nh, n, work);
-  hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(64), 0, s, work, work + kOrderBuckets);
-  hipLaunchKernelGGL(order_scatter_kernel, dim3(grid), dim3(256), 0, s, nh, n,
-                     work + kOrderBuckets, order);
+  hipLaunchKernelGGL(order_count_kernel, dim3(grid), dim3(256), 0, s, nh, n, chunk, work);
+  hipLaunchKernelGGL(order_plan_kernel, dim3(1), dim3(64), 0, s, n, work);
+  hipLaunchKernelGGL(order_blockcount_kernel, dim3(grid), dim3(256), 0, s, nh, n, chunk, work);
+  hipLaunchKernelGGL(order_blockscan_kernel, dim3(1), dim3(64), 0, s, grid, work);
+  hipLaunchKernelGGL(order_scatter_kernel, dim3(grid), dim3(256), 0, s, nh, n, chunk, work,
+                     order);
   return hipGetLastError();
 }
 

@@ -1,0 +1,104 @@
+"""The Newton-Raphson comparator on the GPU (sfc_chem_step_nr) against the
+CPU reference's NR on the same seeded cells.
+
+NR stops each loop at a relative tolerance (1e-5, 1e-3 after 10 outer
+iterations), so where binary64 rounding flips a convergence decision the
+result moves by up to that tolerance.  Bar: cells the reference determines
+to 1e-12 (rounding spread over three other valid roundings of the
+reference NR) and that take the same substeps and outer iterations match
+to 1e-9 relative; every other cell matches to max(1e-9, 1000 x spread),
+or, where the iteration path differs, to the NR tolerance 1e-3.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from parity_util import compare, host_threads, oracle_net_params, report, worst_of
+from paper_2604_21438_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+NR_TOL = 1e-3
+
+
+def _sfc():
+    import paper_2604_21438_amd as sfc
+    return sfc
+
+
+def _run_nr(cells, dt, factor=1.0, params=None, label=""):
+    import torch
+    sfc = _sfc()
+    print(f"[gpu nr] {label}: n={cells['nh'].shape[0]} dt={dt:.3e} factor={factor}", flush=True)
+    ctx = sfc.Context(dust_factor=factor, params=params)
+    t = sfc.to_device(cells)
+    ctx.step_nr(t, dt)
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in t.items()}
+    out["flags"] = out["flags"].view(np.uint32)
+    ctx.close()
+    return out
+
+
+def _check_nr(cells, dt, factor=1.0, par_over=None, label=""):
+    sfc = _sfc()
+    par = sfc.default_params(**(par_over or {}))
+    gpu = _run_nr(cells, dt, factor, par, label)
+    onet, opar = oracle_net_params(sfc.default_network(), par, factor)
+    ref = oracle.nr_step(cells, dt, onet, opar, host_threads())
+    spread = oracle.rounding_spread(cells, dt, ref, onet, opar, host_threads(), method="nr")
+    errs, exc = compare(gpu, ref)
+    n = cells["nh"].shape[0]
+    report(errs, exc, n, label, gpu, ref, cells)
+    worst = worst_of(errs, n)
+    same_path = (gpu["nsub"] == ref["nsub"]) & (gpu["niter"] == ref["niter"])
+    wc = (spread <= 1e-12) & same_path
+    print(f"[nr] {label}: same path {int(same_path.sum())}/{n}, well-conditioned {int(wc.sum())}, "
+          f"max err there {worst[wc].max() if wc.any() else 0:.2e}; others max {worst[~wc].max() if (~wc).any() else 0:.2e}; "
+          f"NRFAIL gpu {int(((gpu['flags'] & 32) != 0).sum())} ref {int(((ref['flags'] & 32) != 0).sum())}",
+          flush=True)
+    if wc.any():
+        assert worst[wc].max() <= 1e-9, (label, int(np.argmax(np.where(wc, worst, 0))))
+    tol = np.where(same_path, np.maximum(1e-9, 1000.0 * spread), np.maximum(NR_TOL, 1000.0 * spread))
+    bad = np.nonzero(~wc & (worst > tol))[0]
+    assert bad.size == 0, (label, bad[:5], worst[bad[:5]])
+    return gpu, ref
+
+
+def test_nr_small_cells():
+    cells, dt = W.small_cells()
+    sub = {k: np.ascontiguousarray(v[:1024]) for k, v in cells.items()}
+    _check_nr(sub, dt, 1.0, label="NR 1024 cells dt=1kyr")
+
+
+def test_nr_grid128_subsample():
+    cells, dt = W.grid128(n=200_000)
+    sub, _ = W.subsample(cells, 1000, seed=31)
+    _check_nr(sub, dt, 1.0, label="NR grid128 subsample")
+
+
+def test_nr_isothermal_and_evolve_ir():
+    cells, dt = W.small_cells()
+    sub = {k: np.ascontiguousarray(v[:256]) for k, v in cells.items()}
+    _check_nr(sub, dt, 1.0, par_over=dict(thermal_mode=1), label="NR isothermal")
+    rng = np.random.default_rng(5)
+    tir = 10 ** rng.uniform(np.log10(3.0), np.log10(50.0), 256)
+    sub["eir"] = 7.5657e-15 * tir ** 4 / 1e-4
+    _check_nr(sub, dt, 10.0, par_over=dict(ir_mode=1), label="NR EVOLVE IR")
+
+
+def test_nr_invalid_and_empty():
+    import torch
+    sfc = _sfc()
+    cells, dt = W.small_cells()
+    sub = {k: np.ascontiguousarray(v[:8].copy()) for k, v in cells.items()}
+    sub["nh"][2] = -1.0
+    out = _run_nr(sub, dt, label="NR invalid")
+    assert out["flags"][2] == sfc.F_INVALID and out["nsub"][2] == 0
+    assert np.all(out["nsub"][[0, 1, 3, 4, 5, 6, 7]] > 0)
+    ctx = sfc.Context()
+    t = {k: torch.zeros(0, dtype=torch.float64, device="cuda")
+         for k in ("nh", "n_euv", "n_fuv", "zmet", "y_h2", "y_e", "eint", "tdust")}
+    ctx.step_nr(t, 1e9)
+    torch.cuda.synchronize()
+    ctx.close()
