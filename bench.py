@@ -71,7 +71,7 @@ def stats(a):
 def relerr(a, b, floor=1e-20):
     e = np.abs(a - b) / np.maximum(np.abs(b), floor)
     return dict(max=float(np.nanmax(e)), p99=float(np.nanpercentile(e, 99)),
-                median=float(np.nanmedian(e)))
+                median=float(np.nanmedian(e)), frac_above_1e9=float(np.mean(e > 1e-9)))
 
 
 def pct(a, q):
@@ -174,6 +174,42 @@ def served_leg(args, sfc, W, torch):
     return out
 
 
+def nr_leg(args, sfc, cells, dt, torch):
+    """The paper's comparison: LI (dust factor 1 and 1000) against the fully
+    implicit NR solver (realistic C_d) on the first nr_cells cells of the
+    headline population, one binary64 launch each."""
+    m = min(args.nr_cells, cells["nh"].shape[0])
+    sub = {k: np.ascontiguousarray(v[:m]) for k, v in cells.items()}
+    out = dict(cells=m, dt_s=dt)
+    for name, factor, nr in (("li_factor1", 1.0, False), ("li_factor1000", 1000.0, False),
+                             ("nr_factor1", 1.0, True)):
+        ctx = sfc.Context(dust_factor=factor)
+        t = sfc.to_device(sub)
+        stream = torch.cuda.current_stream()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        if nr:
+            ctx.step_nr(t, dt)
+        else:
+            ctx.step(t, dt, sfc.FP64)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        s = e0.elapsed_time(e1) * 1e-3
+        ctx.close()
+        ns = t["nsub"].cpu().numpy().astype(np.int64)
+        it = t["niter"].cpu().numpy().astype(np.int64)
+        fl = t["flags"].cpu().numpy().view(np.uint32)
+        out[name] = dict(value=m / s, seconds=s, nsub_mean=float(ns.mean()), nsub_max=int(ns.max()),
+                         niter_mean=float(it.mean()),
+                         nrfail_fraction=float(((fl & sfc.F_NRFAIL) != 0).mean()))
+        log(f"[bench] {name}: {m} cells in {s:.3f} s")
+    out["li_factor1_over_nr"] = out["li_factor1"]["value"] / out["nr_factor1"]["value"]
+    out["li_factor1000_over_nr"] = out["li_factor1000"]["value"] / out["nr_factor1"]["value"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -183,6 +219,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--nr-cells", type=int, default=262144,
+                    help="cells of the LI-vs-NR comparison (0 skips it)")
     ap.add_argument("--served-requests", type=int, default=120)
     ap.add_argument("--served-plain-requests", type=int, default=40)
     ap.add_argument("--served-max-blocks", type=int, default=256)
@@ -335,6 +373,10 @@ def main():
                                         for k in ("y_h2", "y_e", "y_h", "y_hp", "y_hm", "tgas",
                                                   "tdust")},
                                stats=describe(outmx))
+
+    # ---- LI against the Newton-Raphson comparator on the same cells ----
+    if args.nr_cells > 0:
+        result["li_vs_nr"] = nr_leg(args, sfc, cells, dt, torch)
 
     # ---- served form: AMR-shaped requests with Poisson arrivals ----
     if not args.no_served:
