@@ -210,6 +210,32 @@ def nr_leg(args, sfc, cells, dt, torch):
     return out
 
 
+def collapse_leg(sfc):
+    """Free-fall collapse 1e2 -> 1e11 cm^-3 for Z = 1, 1e-2, 1e-4 (three
+    cells per call, one call per 0.1 t_ff): LI at dust factors 1 and 1000
+    and the NR comparator; wall time per track and how far the factor-1000
+    and NR tracks stray from the factor-1 LI track."""
+    from paper_2604_21438_amd import collapse as CO
+    out = {}
+    tracks = {}
+    for name, factor, method in (("li_factor1", 1.0, "li"), ("li_factor1000", 1000.0, "li"),
+                                 ("nr_factor1", 1.0, "nr")):
+        ctx = sfc.Context(dust_factor=factor)
+        t0 = time.perf_counter()
+        tr = CO.run(CO.gpu_step(ctx, method), CO.initial_parcels())
+        el = time.perf_counter() - t0
+        ctx.close()
+        tracks[name] = tr
+        out[name] = dict(seconds=el, steps=int(tr["nh"].shape[0]), nsub_total=int(tr["nsub"].sum()))
+        log(f"[bench] collapse {name}: {el:.2f} s")
+    base = tracks["li_factor1"]
+    for name in ("li_factor1000", "nr_factor1"):
+        out[name]["max_rel_vs_li_factor1"] = {
+            k: float((np.abs(tracks[name][k] - base[k]) / np.abs(base[k])).max())
+            for k in ("tgas", "tdust", "y_h2")}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -219,6 +245,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-collapse", action="store_true")
     ap.add_argument("--nr-cells", type=int, default=262144,
                     help="cells of the LI-vs-NR comparison (0 skips it)")
     ap.add_argument("--served-requests", type=int, default=120)
@@ -377,6 +404,10 @@ def main():
     # ---- LI against the Newton-Raphson comparator on the same cells ----
     if args.nr_cells > 0:
         result["li_vs_nr"] = nr_leg(args, sfc, cells, dt, torch)
+
+    # ---- one-zone free-fall collapse (hydro-free analogue) ----
+    if not args.no_collapse:
+        result["collapse"] = collapse_leg(sfc)
 
     # ---- served form: AMR-shaped requests with Poisson arrivals ----
     if not args.no_served:

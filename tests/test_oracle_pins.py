@@ -548,3 +548,26 @@ def test_counting_build_counts_work():
     assert np.all(flops > 0)
     per_sub = flops / o["nsub"]
     assert np.all(per_sub > 200) and np.all(per_sub < 20000)
+
+
+def test_collapse_tracks_insensitive_to_dust_capacity():
+    """Free-fall collapse from 1e2 to 1e11 cm^-3 (Z = 1, 1e-2, 1e-4, no
+    external radiation): raising the pseudo dust heat capacity from the
+    realistic 1e4 to 1e7 erg/g/K (the range of the paper's C_d study in the
+    collapse tests) changes the gas and dust temperature tracks by a few
+    per cent at most and H2 by about one per cent."""
+    from paper_2604_21438_amd import collapse as CO
+
+    def track(factor):
+        par = oracle.default_params()
+        par.dust_cap = 1e4 * factor
+        return CO.run(lambda c, dt: oracle.li_step(c, dt, params=par, nthreads=4),
+                      CO.initial_parcels())
+
+    base = track(1.0)
+    assert base["nh"][-1, 0] >= 1e11 and base["nh"].shape[0] > 100
+    for factor in (10.0, 1000.0):
+        t = track(factor)
+        for k, bound in (("tgas", 0.06), ("tdust", 0.02), ("y_h2", 0.03)):
+            r = np.abs(t[k] - base[k]) / np.abs(base[k])
+            assert r.max() <= bound, (factor, k, float(r.max()))
