@@ -236,6 +236,77 @@ def collapse_leg(sfc):
     return out
 
 
+def gmc_leg(args, sfc, W, torch):
+    """One coarse step of a GMC-like AMR hierarchy (levels 0..5, level L
+    advanced 2^L times with dt = 10 kyr / 2^L, Z = 0.1, 64 point sources).
+    Plain path: one call per level substep in Berger-Colella order.  Served
+    form: every level submits its next substep as soon as its previous one
+    is done (the same device buffers carry the state), so the levels overlap
+    on the device; latency per request = done - submit."""
+    levels = W.gmc_levels(target_cells=args.gmc_cells)
+    nl = len(levels)
+    sizes = [lv["cells"]["nh"].shape[0] for lv in levels]
+    updates = sum(m * 2 ** L for L, m in enumerate(sizes))
+    log(f"[bench] gmc hierarchy: cells per level {sizes}, {updates} cell-updates per coarse step")
+    bufs = [sfc.to_device(lv["cells"]) for lv in levels]
+    prist = [{k: b[k].clone() for k in STATE_KEYS} for b in bufs]
+
+    def restore():
+        for b, p in zip(bufs, prist):
+            for k in STATE_KEYS:
+                b[k].copy_(p[k])
+        torch.cuda.synchronize()
+
+    def bc_order(L=0):
+        o = [L]
+        if L + 1 < nl:
+            o += bc_order(L + 1) + bc_order(L + 1)
+        return o
+
+    order = bc_order()
+    out = dict(cells_per_level=sizes, cell_updates_per_coarse_step=updates)
+    factors = (1.0, 1000.0) if args.gmc_both_factors else (1.0,)
+    for factor in factors:
+        ctx = sfc.Context(dust_factor=factor, z_default=0.1,
+                          served_budget_bytes=args.served_budget_mib << 20)
+        legs = {}
+        for prec, pname in ((sfc.FP64, "fp64"), (sfc.MIXED, "mixed")):
+            if prec == sfc.FP64:
+                restore()
+                t0 = time.perf_counter()
+                for L in order:
+                    ctx.step(bufs[L], levels[L]["dt"], prec)
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+                legs[f"plain_{pname}"] = dict(value=updates / el, seconds=el)
+            restore()
+            remaining = [2 ** L for L in range(nl)]
+            inflight = [None] * nl
+            lat = []
+            t0 = time.perf_counter()
+            while any(remaining) or any(t is not None for t in inflight):
+                for L in range(nl):
+                    if inflight[L] is not None:
+                        r = ctx.poll(inflight[L])
+                        if r is not None:
+                            lat.append(r["t_done"] - r["t_submit"])
+                            inflight[L] = None
+                    if inflight[L] is None and remaining[L] > 0:
+                        inflight[L] = ctx.submit(bufs[L], levels[L]["dt"], prec, level=L,
+                                                 sync=False)
+                        remaining[L] -= 1
+                time.sleep(100e-6)
+            el = time.perf_counter() - t0
+            legs[f"served_{pname}"] = dict(value=updates / el, seconds=el,
+                                           latency_ms=dict(p50=pct(lat, 50) * 1e3,
+                                                           p99=pct(lat, 99) * 1e3,
+                                                           max=float(np.max(lat)) * 1e3))
+            log(f"[bench] gmc factor {factor:g} {pname}: served {el:.2f} s")
+        ctx.close()
+        out[f"dust_factor_{factor:g}"] = legs
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -246,6 +317,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-collapse", action="store_true")
+    ap.add_argument("--gmc-cells", type=int, default=1_000_000,
+                    help="cells of the GMC-like hierarchy for the served leg (0 skips it)")
+    ap.add_argument("--gmc-both-factors", action="store_true",
+                    help="run the GMC leg at dust factor 1000 too")
     ap.add_argument("--nr-cells", type=int, default=262144,
                     help="cells of the LI-vs-NR comparison (0 skips it)")
     ap.add_argument("--served-requests", type=int, default=120)
@@ -412,6 +487,10 @@ def main():
     # ---- served form: AMR-shaped requests with Poisson arrivals ----
     if not args.no_served:
         result["served"] = served_leg(args, sfc, W, torch)
+
+    # ---- served form: one coarse step of a GMC-like AMR hierarchy ----
+    if args.gmc_cells > 0:
+        result["served_gmc"] = gmc_leg(args, sfc, W, torch)
 
     # ---- CPU reference on a sample of the same cells ----
     if not args.no_cpu:

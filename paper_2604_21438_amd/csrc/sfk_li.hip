@@ -214,9 +214,8 @@ __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, d
 
   // ---- steady-state H- and the abundances (values in binary64) ----
   R ratio = R(0), dratio = R(0);
-  TF<R> k2;
+  TF<R> k2, k3;  // k3 is used again by Gamma_1 below
   {
-    TF<R> k3;
     k2k3<R>(T64, lnT64, iT64, k2, k3);
     k2.v *= R(nt.rm[2]);
     k2.t *= R(nt.rm[2]);
@@ -290,11 +289,8 @@ __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, d
   const R g1 = R(nt.pm[0]) * evn;  // Gamma_1 prefactor
   // H3 in Gamma_1: 3.73 eV per H2 formed through H-
   {
-    TF<R> k2b, k3;
-    k2k3<R>(T64, lnT64, iT64, k2b, k3);
-    k3.v *= R(nt.rm[3]);
-    k3.t *= R(nt.rm[3]);
-    acc(q, g1 * R(3.73), k3, f * (YH * YHM));
+    const TF<R> k3m{k3.v * R(nt.rm[3]), k3.t * R(nt.rm[3])};
+    acc(q, g1 * R(3.73), k3m, f * (YH * YHM));
   }
   const G<R> H2H = Y2 * YH;
   const G<R> H22 = Y2 * Y2;

@@ -220,3 +220,113 @@ def poisson_arrivals(n: int, rate: float, seed: int = 3):
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(21438 + seed)))
     gaps = rng.exponential(1.0 / rate, n)
     return np.concatenate([[0.0], np.cumsum(gaps[1:])])
+
+
+def _gaussian_field(g, side: int, slope: float = 11.0 / 3.0):
+    """Unit-variance Gaussian random field on a periodic side^3 grid with
+    power spectrum P(k) ~ |k|^-slope (random phases), via FFT."""
+    k = np.fft.fftfreq(side) * side
+    kx, ky, kz = np.meshgrid(k, k, np.fft.rfftfreq(side) * side, indexing="ij")
+    kk = np.sqrt(kx * kx + ky * ky + kz * kz)
+    amp = np.zeros_like(kk)
+    amp[kk > 0] = kk[kk > 0] ** (-slope / 2.0)
+    spec = amp * (g.normal(size=kk.shape) + 1j * g.normal(size=kk.shape))
+    f = np.fft.irfftn(spec, s=(side, side, side))
+    return (f - f.mean()) / f.std()
+
+
+def gmc_levels(target_cells: int = 4_000_000, base_side: int = 64, n_levels: int = 6,
+               sigma: float = 2.5, n_sources: int = 64, zmet: float = 0.1, seed_offset: int = 0):
+    """A GMC-like AMR hierarchy of 8^3-cell blocks for the served form.
+
+    Level 0 covers the unit cube with base_side^3 cells; ln n_H = ln 100 +
+    sigma g on the level-0 grid (g a Gaussian random field, P(k) ~ k^-11/3).
+    A block of level L is refined into 8 blocks of level L + 1 (twice the
+    resolution) where its densest cell exceeds n0 4^L; child cells take
+    their parent cell's density times exp(0.5 G), G a fresh unit normal per
+    cell.  n0 is bisected so that the hierarchy holds target_cells +- 2 %
+    (levels 1..n_levels-1 non-empty when possible).  T, abundances as the
+    uniform population; 64 point sources at uniform positions give N_EUV =
+    sum A_s (h/max(r, h))^2 and N_FUV = r_s times that (h the level-0 cell,
+    A_s ~ logU[1, 100] cm^-3, r_s ~ logU[1, 10]); Z = zmet.
+
+    Returns a list of levels, each a dict with 'cells' (SoA, blocks
+    concatenated), 'dt' = 10 kyr / 2^L, 'blocks' and 'level'."""
+    g = _streams(4, 8, seed_offset)
+    base = np.exp(np.log(100.0) + sigma * _gaussian_field(g[0], base_side))
+    nb0 = base_side // BLOCK
+    # level-0 blocks: (corner index in level-L cell units, densities 8x8x8)
+    def blocks_of(field, side):
+        nb = side // BLOCK
+        f = field.reshape(nb, BLOCK, nb, BLOCK, nb, BLOCK).transpose(0, 2, 4, 1, 3, 5)
+        corners = np.stack(np.meshgrid(np.arange(nb), np.arange(nb), np.arange(nb),
+                                       indexing="ij"), -1).reshape(-1, 3) * BLOCK
+        return corners, f.reshape(-1, BLOCK, BLOCK, BLOCK)
+
+    cap = 4 * target_cells
+
+    def build(n0):
+        """The hierarchy for threshold n0, or None once it exceeds cap cells."""
+        levels = []
+        corners, dens = blocks_of(base, base_side)
+        total = 0
+        rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(21438 + 400 + seed_offset)))
+        for L in range(n_levels):
+            levels.append((corners, dens))
+            total += dens.size
+            if L == n_levels - 1:
+                break
+            refine = dens.reshape(dens.shape[0], -1).max(axis=1) > n0 * 4.0 ** L
+            if not refine.any():
+                break
+            if total + 8 * int(refine.sum()) * BLOCK ** 3 > cap:
+                return None
+            pc, pd = corners[refine], dens[refine]
+            # each parent block -> 8 children at twice the resolution
+            up = pd.repeat(2, axis=1).repeat(2, axis=2).repeat(2, axis=3)  # (m, 16, 16, 16)
+            up = up * np.exp(0.5 * rng.normal(size=up.shape))
+            ch_c, ch_d = [], []
+            for ox in (0, 1):
+                for oy in (0, 1):
+                    for oz in (0, 1):
+                        ch_c.append(2 * pc + BLOCK * np.array([ox, oy, oz]))
+                        ch_d.append(up[:, ox * BLOCK:(ox + 1) * BLOCK, oy * BLOCK:(oy + 1) * BLOCK,
+                                       oz * BLOCK:(oz + 1) * BLOCK])
+            corners, dens = np.concatenate(ch_c), np.concatenate(ch_d)
+        return levels
+
+    lo, hi = 1.0, 1.0e12
+    levels = None
+    for _ in range(80):
+        mid = np.sqrt(lo * hi)
+        trial = build(mid)
+        total = cap + 1 if trial is None else sum(d.size for _, d in trial)
+        if trial is not None:
+            levels = trial
+        if abs(total - target_cells) <= 0.02 * target_cells:
+            break
+        if total > target_cells:
+            lo = mid
+        else:
+            hi = mid
+    if levels is None:
+        levels = build(hi)
+    src = g[1].uniform(0.0, 1.0, (n_sources, 3))
+    amp = 10.0 ** g[2].uniform(0.0, 2.0, n_sources)
+    ratio = 10.0 ** g[3].uniform(0.0, 1.0, n_sources)
+    h0 = 1.0 / base_side
+    out = []
+    for L, (corners, dens) in enumerate(levels):
+        m = dens.shape[0] * BLOCK ** 3
+        hL = h0 / 2.0 ** L
+        i = np.arange(BLOCK ** 3)
+        local = np.stack([i // (BLOCK * BLOCK), (i // BLOCK) % BLOCK, i % BLOCK], 1)
+        pos = ((corners[:, None, :] + local[None, :, :]).reshape(-1, 3) + 0.5) * hL
+        nh = dens.reshape(-1)
+        tg = 10.0 ** g[4].uniform(1.0, 4.0, m)
+        y_h2, y_e = _abundances(g[5], g[6], m)
+        n_euv = point_source_field(pos, src, amp, h0)
+        n_fuv = point_source_field(pos, src, amp * ratio, h0)
+        cells = _pack(nh, n_euv, n_fuv, np.full(m, zmet), y_h2, y_e, tg, tg.copy())
+        out.append(dict(cells=cells, dt=10.0 * KYR / 2.0 ** L, blocks=dens.shape[0], level=L))
+    return out
