@@ -80,6 +80,7 @@ bool fill_par(const sfc_params& p, double z_default, double cd, const sfk::Net& 
   o.t_cmb = p.t_cmb;
   o.y_he = p.y_he;
   o.gm1 = p.gamma_ad - 1.0;
+  o.igm1 = 1.0 / o.gm1;
   o.cd = cd;
   o.z_default = z_default;
   o.n_cyc = p.n_cyc;

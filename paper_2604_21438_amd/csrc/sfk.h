@@ -31,6 +31,7 @@ struct Net {
 
 struct Par {
   double f_chem, y_abs, newton_rtol, c_red, t_cmb, y_he, gm1;  // gm1 = gamma - 1
+  double igm1;           // 1 / (gamma - 1)
   double cd;             // C_d [erg/g/K]
   double z_default;
   double hm_ratio_max;   // upper bound of y_H-/y_e = k_H2/k_H3 over the rate range

@@ -59,6 +59,22 @@ __device__ inline double frcp(double x) {
   return fma(r, e, r);
 }
 
+// sqrt(x) for positive, finite, normal x: hardware 1/sqrt estimate, one
+// coupled Newton step on (sqrt x, 1/(2 sqrt x)) and two residual
+// corrections g += (x - g^2) h (Goldschmidt's iteration, Markstein's form);
+// the library sqrt adds range scaling and special-value handling on top.
+__device__ inline double fsqrt(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+
 template <class R>
 struct Mth;
 template <>
@@ -67,8 +83,9 @@ struct Mth<double> {
   __device__ static double ex(double x) { return exp(x); }
   __device__ static double lg(double x) { return log(x); }
   __device__ static double lg1p(double x) { return log1p(x); }
-  __device__ static double sq(double x) { return sqrt(x); }
-  // every quotient in the assembly has a positive, normal denominator
+  // every root and quotient in the assembly has a positive, normal argument
+  // (temperatures are clamped to [1, 1e8] K or floored at T_CMB)
+  __device__ static double sq(double x) { return fsqrt(x); }
   __device__ static double dv(double a, double b) { return a * frcp(b); }
 };
 template <>
@@ -206,7 +223,7 @@ __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, d
   if (Tc < 1.0) { Tc = 1.0; clampT = R(0); }
   if (Tc > 1.0e8) { Tc = 1.0e8; clampT = R(0); }
   const double T64 = Tc;
-  const double iT64 = 1.0 / Tc;
+  const double iT64 = frcp(Tc);
   const double lnT64 = log(Tc);
   const R T = R(T64);
   const R n = R(ck.n);
@@ -277,7 +294,7 @@ __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, d
   {
     const double e1x = 400.0 * iT64;
     const R e1 = M::ea(-e1x * e1x);
-    const double iT12 = 1.0 / (T64 + 1200.0);
+    const double iT12 = frcp(T64 + 1200.0);
     const R e2 = M::ea(-12000.0 * iT12);
     G<R> nD{R(0), R(0), R(0), R(0)};
     acc(nD, R(1.6) * n, TF<R>{e1, e1 * R(2.0 * e1x * e1x * iT64)}, YH);
@@ -323,7 +340,7 @@ __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, d
                         double(M::lg1p(-eb));  // ln 8.125e-8
     const double ebd = double(eb);
     const double dlnkh = -0.5 * iT64 + 5.2e4 * iT64 * iT64 -
-                         ebd * 6000.0 * iT64 * iT64 / (1.0 - ebd);
+                         ebd * 6000.0 * iT64 * iT64 * frcp(1.0 - ebd);
     const double t = lnT64 * (1.0 / LN10) - 4.0;
     const R ncr = M::ea(LN10 * (4.845 - 1.3 * t + 1.62 * t * t));
     const double a = double(ncr * M::dv(R(1), ncr + n));
@@ -481,7 +498,7 @@ __device__ inline void dust_eval(const Net& nt, const Par& pr, double Tg_, doubl
   const R Tg = R(Tg_), Td = R(Td_);
   const R iTg = M::dv(R(1), Tg);
   d.G = R(nt.pm[13] * RG * ck.n) * M::sq(Tg * R(1.0 / THIGH));
-  d.gd = R(1) - R(0.8) * M::ea(-TLOW / Tg_);
+  d.gd = R(1) - R(0.8) * M::ea(-TLOW * frcp(Tg_));
   const R rr = Td * iTg - R(1);
   d.zeta = R(0.5) * d.gd * rr + (d.gd - R(1)) * R(TLOW) * iTg * rr - d.gd;
   R kd, dkd;
@@ -556,7 +573,7 @@ __device__ inline void solve3(double a00, double a01, double a02, double a10, do
     a22 = a22 - m * a12;
     b2 = b2 - m * b1;
   }
-  x2 = b2 / a22;
+  x2 = b2 * frcp(a22);
   x1 = (b1 - a12 * x2) * i11;
   x0 = (b0 - a01 * x1 - a02 * x2) * i00;
 }
@@ -573,7 +590,7 @@ __device__ inline void solve2(double a00, double a01, double a10, double a11, do
   const double m = a10 * i00;
   a11 = a11 - m * a01;
   b1 = b1 - m * b0;
-  x1 = b1 / a11;
+  x1 = b1 * frcp(a11);
   x0 = (b0 - a01 * x1) * i00;
 }
 
@@ -598,7 +615,7 @@ __device__ inline double ntot_rel(const Par& pr, double y2, double ye) {
 
 // E_th / (k_B n) per unit temperature: n_tot / (gamma - 1)
 __device__ inline double cvk(const Par& pr, double y2, double ye) {
-  return ntot_rel(pr, y2, ye) / pr.gm1;
+  return ntot_rel(pr, y2, ye) * pr.igm1;
 }
 
 // Conservation renormalisation (binary64): clamp the unknowns, rebuild
@@ -638,13 +655,13 @@ __device__ inline void renormalise(const Net& nt, const Par& pr, Lane& L, bool i
 // kappa in binary64 for the tight Newton
 __device__ inline void kappa_d(const Net& nt, double T, double& k, double& dk) {
   const double x = T * nt.kap_tn;
-  const double d = 1.0 + x * x;
-  k = nt.kap_max * x * x / d;
-  dk = nt.kap_max * 2.0 * x / (d * d) * nt.kap_tn;
+  const double id = frcp(1.0 + x * x);
+  k = nt.kap_max * x * x * id;
+  dk = nt.kap_max * 2.0 * x * (id * id) * nt.kap_tn;
 }
 
 struct TightC {
-  double td0, tg0, e0, h, ggd, dg, P, qd, absfix, kir, euv, cd;
+  double td0, tg0, e0, h, ggd, dg, P, iqd, absfix, kir, euv, cd;  // iqd = 1 / q_d
 };
 
 __device__ inline void tight_phi(const Net& nt, const Par& pr, const TightC& t, double x,
@@ -658,9 +675,9 @@ __device__ inline void tight_phi(const Net& nt, const Par& pr, const TightC& t, 
   const double demis = ac * x3 * (4.0 * k + dk * x);
   double ab, dab;
   if (pr.ir_mode == 1) {
-    const double E = (t.e0 + t.P * emis) / t.qd;
+    const double E = (t.e0 + t.P * emis) * t.iqd;
     ab = t.kir * ctil * E;
-    dab = t.kir * ctil * t.P * demis / t.qd;
+    dab = t.kir * ctil * t.P * demis * t.iqd;
   } else {
     ab = t.absfix;
     dab = 0.0;
@@ -676,7 +693,7 @@ template <class R>
 __device__ inline void dust_tight(const Net& nt, const Par& pr, Lane& L, double h) {
   const double knb = KB * L.ck.n;
   const double cv = knb * cvk(pr, L.y2, L.ye);
-  const double Tg0 = L.E / cv;
+  const double Tg0 = L.E * frcp(cv);
   Dust<R> d;
   dust_eval<R>(nt, pr, Tg0, L.Td, L.Eir, L.ck, d);
   TightC t;
@@ -686,13 +703,14 @@ __device__ inline void dust_tight(const Net& nt, const Par& pr, Lane& L, double 
   t.h = h;
   t.cd = pr.cd;
   t.euv = L.ck.euv;
-  const double alpha = cv / L.ck.rho;
+  const double alpha = cv * frcp(L.ck.rho);
   t.ggd = double(d.G) * double(d.gd);
   const double w = h * L.ck.fd * t.ggd;
-  t.dg = alpha / (alpha + w);
+  const double iaw = frcp(alpha + w);
+  t.dg = alpha * iaw;
   t.P = h * L.ck.rho * L.ck.fd;
   t.kir = double(d.kir);
-  t.qd = 1.0 + t.P * pr.c_red * CL * t.kir;
+  t.iqd = frcp(1.0 + t.P * pr.c_red * CL * t.kir);
   t.absfix = double(d.absir);
 
   double lo = pr.t_cmb, hi, f, fp, x;
@@ -716,7 +734,7 @@ __device__ inline void dust_tight(const Net& nt, const Par& pr, Lane& L, double 
     for (it = 1; it <= pr.newton_max; ++it) {
       tight_phi(nt, pr, t, x, f, fp);
       if (f == 0.0) { conv = true; break; }
-      double xn = x - f / fp;
+      double xn = x - f * frcp(fp);  // Phi' >= C_d > 0
       if (f < 0.0) {
         lo = x;
         if (!(xn < hi)) xn = hi;
@@ -728,7 +746,7 @@ __device__ inline void dust_tight(const Net& nt, const Par& pr, Lane& L, double 
       x = xn;
       if (fabs(dx) <= pr.newton_rtol * x) {
         tight_phi(nt, pr, t, x, f, fp);
-        xn = x - f / fp;
+        xn = x - f * frcp(fp);
         if (xn >= lo && xn <= hi) x = xn;
         conv = true;
         break;
@@ -738,11 +756,11 @@ __device__ inline void dust_tight(const Net& nt, const Par& pr, Lane& L, double 
   }
   if (!conv) L.fl |= F_NOCONV;
   L.nit += it;
-  const double tg = (alpha * t.tg0 + w * x) / (alpha + w);
+  const double tg = (alpha * t.tg0 + w * x) * iaw;
   if (pr.ir_mode == 1) {
     double k, dk;
     kappa_d(nt, x, k, dk);
-    L.Eir = (t.e0 + t.P * k * ARAD * CL * x * x * x * x) / t.qd;
+    L.Eir = (t.e0 + t.P * k * ARAD * CL * x * x * x * x) * t.iqd;
   }
   L.Td = x;
   L.E = L.E + cv * (tg - Tg0);
@@ -753,14 +771,14 @@ template <class R>
 __device__ inline void dust_linear(const Net& nt, const Par& pr, Lane& L, double h) {
   const double knb = KB * L.ck.n;
   const double cv = knb * cvk(pr, L.y2, L.ye);
-  const double Tg = L.E / cv;
+  const double Tg = L.E * frcp(cv);
   Dust<R> d;
   dust_eval<R>(nt, pr, Tg, L.Td, L.Eir, L.ck, d);
   const double ctil = pr.c_red * CL;
   const double ac = ARAD * CL;
   const double G = double(d.G), gd = double(d.gd), zeta = double(d.zeta);
   const double betad = double(d.betad), betair = double(d.betair);
-  const double alpha = cv / L.ck.rho;
+  const double alpha = cv * frcp(L.ck.rho);
   const double td3 = L.Td * L.Td * L.Td;
   const double rho = L.ck.rho, fd = L.ck.fd, cd = pr.cd;
   const double A00 = cd + h * G * gd + h * ac * td3 * betad;
@@ -813,8 +831,9 @@ __device__ bool subcycle(const Net& nt, const Par& pr, Lane& L) {
   const bool dust_on = (pr.dust_mode == 0) && !iso;
   const double knb = KB * L.ck.n;
   const double ntr = ntot_rel(pr, L.y2, L.ye);
-  const double Ek = L.E / knb;                  // E_th / (k_B n) [K]
-  const double T = iso ? L.Tiso : Ek * pr.gm1 / ntr;
+  const double Ek = L.E * frcp(knb);            // E_th / (k_B n) [K]
+  const double intr = frcp(ntr);
+  const double T = iso ? L.Tiso : Ek * pr.gm1 * intr;
 
   Chem<R> ch;
   assemble<R>(nt, pr, L.y2, L.ye, L.Td, T, L.ck, ch);
@@ -826,10 +845,10 @@ __device__ bool subcycle(const Net& nt, const Par& pr, Lane& L) {
     dust_eval<R>(nt, pr, T, L.Td, L.Eir, L.ck, d);
     // gas-grain exchange rho S_g / (k_B n) [K/s]
     qgg = double(d.Sg) * (L.ck.rho / knb);
-    const double alpha = knb * (ntr / pr.gm1) / L.ck.rho;
-    nu_dust = fabs(double(d.Sd)) / (pr.cd * L.Td);
-    nu_dust = fmax(nu_dust, fabs(double(d.Sg)) / (alpha * T));
-    if (pr.ir_mode == 1) nu_dust = fmax(nu_dust, fabs(double(d.Sir)) / L.Eir);
+    const double alpha = knb * (ntr * pr.igm1) * frcp(L.ck.rho);
+    nu_dust = fabs(double(d.Sd)) * frcp(pr.cd * L.Td);
+    nu_dust = fmax(nu_dust, fabs(double(d.Sg)) * frcp(alpha * T));
+    if (pr.ir_mode == 1) nu_dust = fmax(nu_dust, fabs(double(d.Sir)) * frcp(L.Eir));
   }
   const bool tight = dust_on && (L.rem * nu_dust / pr.f_chem >= double(pr.n_cyc));
   if (tight) L.fl |= F_TIGHT;
@@ -841,7 +860,8 @@ __device__ bool subcycle(const Net& nt, const Par& pr, Lane& L) {
 
   double h;
   bool last = false;
-  h = nu > 0.0 ? pr.f_chem / nu : L.rem;
+  // below 1e-300 the step is far beyond any interval: take the rest
+  h = nu > 1e-300 ? pr.f_chem * frcp(nu) : L.rem;
   if (h >= L.rem) {
     h = L.rem;
     last = true;
@@ -856,7 +876,7 @@ __device__ bool subcycle(const Net& nt, const Par& pr, Lane& L) {
 
   // chemistry + energy: (I - h J) du = h f, u = (y_H2, y_e, E/E_ref)
   {
-    const double Tn = T * frcp(ntr);
+    const double Tn = T * intr;
     const double dTy2 = iso ? 0.0 : Tn;
     const double dTye = iso ? 0.0 : -Tn;
     const double dTu = iso ? 0.0 : T;
