@@ -34,7 +34,7 @@ extern "C" {
 
 /* Version of sfc_network and sfc_params (both checked through
  * sfc_network.abi_version). */
-#define SFC_ABI_VERSION 2u
+#define SFC_ABI_VERSION 3u
 
 enum {
   SFC_OK = 0,
@@ -52,10 +52,26 @@ typedef enum { SFC_IR_FIXED = 0, SFC_IR_EVOLVE = 1 } sfc_ir_mode;
 typedef enum { SFC_THERMAL_EVOLVE = 0, SFC_THERMAL_ISOTHERMAL = 1 } sfc_thermal_mode;
 typedef enum { SFC_DUST_EVOLVE = 0, SFC_DUST_FROZEN = 1 } sfc_dust_mode;
 /* Order in which the plain step hands cells to GPU lanes (scheduling only;
- * every cell's result is the same in both).  DENSITY starts the densest
- * cells first: their stiffer chemistry and gas-grain coupling need the most
- * subcycles, and starting them early keeps them off the end of the call. */
-typedef enum { SFC_DISPATCH_INDEX = 0, SFC_DISPATCH_DENSITY = 1 } sfc_dispatch;
+ * every cell's result is bitwise the same in all three).
+ *   INDEX     cells in index order.
+ *   DENSITY   the densest cells first: their stiffer chemistry and
+ *             gas-grain coupling need the most subcycles, and starting them
+ *             early keeps them off the end of the call.
+ *   PROGRESS  two passes.  The first runs every cell (densest first) for
+ *             at most sfc_params.phase_nsub subcycles; a cell still running
+ *             then is suspended (its state written back in place, the rest
+ *             of it kept by the context).  The second resumes the suspended
+ *             cells, longest estimated remainder first, the estimate being
+ *             the subcycles still needed at the cell's pace so far.  Cells
+ *             that cost ~1e5 subcycles then start first instead of wherever
+ *             density puts them.  Uses 36 B of context-owned device memory
+ *             per cell (allocated at the first call that needs more).
+ *   NR comparator calls (sfc_chem_step_nr) use DENSITY under PROGRESS. */
+typedef enum {
+  SFC_DISPATCH_INDEX = 0,
+  SFC_DISPATCH_DENSITY = 1,
+  SFC_DISPATCH_PROGRESS = 2
+} sfc_dispatch;
 
 enum { SFC_NREAC = 12, SFC_NPROC = 14, SFC_NLINE = 5 };
 
@@ -103,7 +119,8 @@ typedef struct {
   int32_t ir_mode;     /* sfc_ir_mode [SFC_IR_FIXED]                      */
   int32_t thermal_mode;/* sfc_thermal_mode [SFC_THERMAL_EVOLVE]           */
   int32_t dust_mode;   /* sfc_dust_mode [SFC_DUST_EVOLVE]                 */
-  int32_t dispatch;    /* sfc_dispatch [SFC_DISPATCH_DENSITY]             */
+  int32_t dispatch;    /* sfc_dispatch [SFC_DISPATCH_PROGRESS]            */
+  int32_t phase_nsub;  /* PROGRESS: subcycles of the first pass, >= 1 [4096] */
 } sfc_params;
 
 void sfc_network_default(sfc_network* net);

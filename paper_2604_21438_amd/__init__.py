@@ -17,13 +17,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsfchem.so")
 
 FP64, MIXED = 0, 1
-DISPATCH_INDEX, DISPATCH_DENSITY = 0, 1
+DISPATCH_INDEX, DISPATCH_DENSITY, DISPATCH_PROGRESS = 0, 1, 2
 IR_FIXED, IR_EVOLVE = 0, 1
 THERMAL_EVOLVE, THERMAL_ISOTHERMAL = 0, 1
 DUST_EVOLVE, DUST_FROZEN = 0, 1
 F_CAP, F_TIGHT, F_NOCONV, F_INVALID, F_FLOOR, F_NRFAIL = 1, 2, 4, 8, 16, 32
 OK, E_INVAL, E_NOMEM, E_BUDGET, E_DEVICE, E_PENDING, E_VERSION, E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
-ABI_VERSION = 2
+ABI_VERSION = 3
 NREAC, NPROC, NLINE = 12, 14, 5
 
 _d = C.c_double
@@ -49,7 +49,7 @@ class SfcParams(C.Structure):
         ("y_he", _d), ("gamma_ad", _d),
         ("n_cyc", C.c_int32), ("n_sub_max", C.c_int32), ("newton_max", C.c_int32),
         ("ir_mode", C.c_int32), ("thermal_mode", C.c_int32), ("dust_mode", C.c_int32),
-        ("dispatch", C.c_int32),
+        ("dispatch", C.c_int32), ("phase_nsub", C.c_int32),
     ]
 
 

@@ -110,10 +110,13 @@ struct sfc_ctx {
   unsigned long long* d_counter = nullptr;
   sfk::Net* d_net = nullptr;  // device copies read by the kernels
   sfk::Par* d_par = nullptr;
-  int dispatch = SFC_DISPATCH_DENSITY;
+  int dispatch = SFC_DISPATCH_PROGRESS;
+  int32_t phase_nsub = 4096;
   int32_t* d_order = nullptr;  // density dispatch: cell order and bucket counters
   int64_t order_cap = 0;
   uint32_t* d_buckets = nullptr;
+  void* d_sus = nullptr;  // progress dispatch: suspended-cell slots (one block)
+  int64_t sus_cap = 0;
   int cus = 0;
   int bpc[3] = {1, 1, 1};  // blocks per CU: LI binary64, LI mixed, NR
   int refill_min = 1;
@@ -137,6 +140,7 @@ struct DeviceGuard {
 
 // Frees a context's device buffers and the context itself.
 void release(sfc_ctx* ctx) {
+  if (ctx->d_sus) (void)hipFree(ctx->d_sus);
   if (ctx->d_order) (void)hipFree(ctx->d_order);
   if (ctx->d_buckets) (void)hipFree(ctx->d_buckets);
   if (ctx->d_counter) (void)hipFree(ctx->d_counter);
@@ -233,7 +237,8 @@ void sfc_params_default(sfc_params* p) {
   p->ir_mode = SFC_IR_FIXED;
   p->thermal_mode = SFC_THERMAL_EVOLVE;
   p->dust_mode = SFC_DUST_EVOLVE;
-  p->dispatch = SFC_DISPATCH_DENSITY;
+  p->dispatch = SFC_DISPATCH_PROGRESS;
+  p->phase_nsub = 4096;
 }
 
 int sfc_chem_init(const sfc_network* net_in, double z_default, double dust_cap_factor,
@@ -256,7 +261,10 @@ int sfc_chem_init(const sfc_network* net_in, double z_default, double dust_cap_f
   sfk::Par kpar;
   if (!fill_net(net, knet) || !fill_par(p, z_default, dust_cap_factor * 1.0e4, knet, kpar))
     return SFC_E_INVAL;
-  if (p.dispatch != SFC_DISPATCH_INDEX && p.dispatch != SFC_DISPATCH_DENSITY) return SFC_E_INVAL;
+  if (p.dispatch != SFC_DISPATCH_INDEX && p.dispatch != SFC_DISPATCH_DENSITY &&
+      p.dispatch != SFC_DISPATCH_PROGRESS)
+    return SFC_E_INVAL;
+  if (p.dispatch == SFC_DISPATCH_PROGRESS && p.phase_nsub < 1) return SFC_E_INVAL;
   if (hip_device < 0) return SFC_E_INVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device >= ndev) return SFC_E_DEVICE;
@@ -266,6 +274,7 @@ int sfc_chem_init(const sfc_network* net_in, double z_default, double dust_cap_f
   ctx->net = knet;
   ctx->par = kpar;
   ctx->dispatch = p.dispatch;
+  ctx->phase_nsub = p.phase_nsub;
   DeviceGuard g(hip_device);
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) {
@@ -321,6 +330,55 @@ int sfc_chem_init(const sfc_network* net_in, double z_default, double dust_cap_f
 
 namespace {
 
+// Order buffer (cell order, bucket counters) of density and progress
+// dispatch, grown to n cells.
+bool ensure_order(sfc_ctx* ctx, int64_t n) {
+  if (n > ctx->order_cap) {
+    if (ctx->d_order) (void)hipFree(ctx->d_order);
+    ctx->d_order = nullptr;
+    ctx->order_cap = 0;
+    if (hipMalloc(&ctx->d_order, size_t(n) * sizeof(int32_t)) != hipSuccess) return false;
+    ctx->order_cap = n;
+  }
+  if (!ctx->d_buckets &&
+      hipMalloc(&ctx->d_buckets, sfk::kOrderWork * sizeof(uint32_t)) != hipSuccess)
+    return false;
+  return true;
+}
+
+// Suspended-cell slots of progress dispatch, one device block grown to n
+// slots: the slot counter, then rem, tiso (binary64), cell, nsub, nit,
+// flags, bucket (32-bit), each array 256-byte aligned.
+bool ensure_suspended(sfc_ctx* ctx, int64_t n, sfk::Suspended& sus) {
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  if (n > ctx->sus_cap) {
+    if (ctx->d_sus) (void)hipFree(ctx->d_sus);
+    ctx->d_sus = nullptr;
+    ctx->sus_cap = 0;
+    const size_t bytes = 256 + 2 * al(size_t(n) * 8) + 5 * al(size_t(n) * 4);
+    if (hipMalloc(&ctx->d_sus, bytes) != hipSuccess) return false;
+    ctx->sus_cap = n;
+  }
+  const size_t cap = size_t(ctx->sus_cap);
+  char* b = static_cast<char*>(ctx->d_sus);
+  sus.count = reinterpret_cast<unsigned long long*>(b);
+  b += 256;
+  sus.rem = reinterpret_cast<double*>(b);
+  b += al(cap * 8);
+  sus.tiso = reinterpret_cast<double*>(b);
+  b += al(cap * 8);
+  sus.cell = reinterpret_cast<int32_t*>(b);
+  b += al(cap * 4);
+  sus.nsub = reinterpret_cast<int32_t*>(b);
+  b += al(cap * 4);
+  sus.nit = reinterpret_cast<int32_t*>(b);
+  b += al(cap * 4);
+  sus.fl = reinterpret_cast<uint32_t*>(b);
+  b += al(cap * 4);
+  sus.bucket = reinterpret_cast<int32_t*>(b);
+  return true;
+}
+
 // Plain path launch; method 0 = LI binary64, 1 = LI mixed, 2 = NR binary64.
 int step_launch(sfc_ctx* ctx, const sfc_cells* cells, double dt, int method, void* hip_stream,
                 const char* who) {
@@ -346,29 +404,52 @@ int step_launch(sfc_ctx* ctx, const sfc_cells* cells, double dt, int method, voi
   const int grid = int(need < cap ? need : cap);
   a.order = nullptr;
   a.dense = nullptr;
-  // density dispatch pays off once lanes take several cells each
-  if (ctx->dispatch == SFC_DISPATCH_DENSITY && cells->n > 2 * int64_t(grid) * sfk::kBlock &&
-      cells->n < (int64_t(1) << 31)) {
-    if (cells->n > ctx->order_cap) {
-      if (ctx->d_order) (void)hipFree(ctx->d_order);
-      ctx->d_order = nullptr;
-      ctx->order_cap = 0;
-      if (hipMalloc(&ctx->d_order, size_t(cells->n) * sizeof(int32_t)) != hipSuccess)
-        return fail(ctx, SFC_E_NOMEM, "sfc_chem_step: dispatch order buffer");
-      ctx->order_cap = cells->n;
-    }
-    if (!ctx->d_buckets &&
-        hipMalloc(&ctx->d_buckets, sfk::kOrderWork * sizeof(uint32_t)) != hipSuccess)
-      return fail(ctx, SFC_E_NOMEM, "sfc_chem_step: dispatch buckets");
+  a.budget = 0;
+  a.resume = 0;
+  a.fine = 0;
+  a.limit = nullptr;
+  a.sus = sfk::Suspended{};
+  const bool small_ids = cells->n < (int64_t(1) << 31);
+  const bool progress = ctx->dispatch == SFC_DISPATCH_PROGRESS && method != 2 && small_ids;
+  // density order pays off once lanes take several cells each
+  const bool density = ctx->dispatch != SFC_DISPATCH_INDEX && small_ids &&
+                       cells->n > 2 * int64_t(grid) * sfk::kBlock;
+  if ((density || progress) && !ensure_order(ctx, cells->n))
+    return fail(ctx, SFC_E_NOMEM, std::string(who) + ": dispatch order buffer");
+  if (density) {
     const hipError_t oe = sfk::launch_order(cells->nh, cells->n, ctx->d_order, ctx->d_buckets, s);
     if (oe != hipSuccess) return hip_fail(ctx, oe, "dispatch order launch");
     a.order = ctx->d_order;
     a.dense = ctx->d_buckets + sfk::kOrderDenseWord;
   }
+  if (progress) {
+    if (!ensure_suspended(ctx, cells->n, a.sus))
+      return fail(ctx, SFC_E_NOMEM, std::string(who) + ": suspended-cell slots");
+    a.budget = ctx->phase_nsub;
+    const hipError_t re = sfk::launch_reset(a.sus.count, s);
+    if (re != hipSuccess) return hip_fail(ctx, re, "reset launch");
+  }
   hipError_t e = sfk::launch_reset(ctx->d_counter, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "reset launch");
   e = method == 2 ? sfk::launch_step_nr(a, grid, s) : sfk::launch_step(a, method, grid, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "step launch");
+  if (progress) {
+    // second pass: the suspended cells, longest estimated remainder first
+    e = sfk::launch_progress_order(a.sus, dt, ctx->par.n_sub_max, ctx->sus_cap, ctx->d_buckets,
+                                   ctx->d_order, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "progress order launch");
+    sfk::Args b = a;
+    b.budget = 0;
+    b.resume = 1;
+    b.fine = 1;
+    b.order = ctx->d_order;
+    b.dense = nullptr;
+    b.limit = a.sus.count;
+    e = sfk::launch_reset(ctx->d_counter, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "reset launch");
+    e = sfk::launch_step(b, method, grid, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "step launch");
+  }
   return SFC_OK;
 }
 

@@ -47,6 +47,17 @@ struct Cells {
   uint32_t *flags;
 };
 
+// Cells suspended by the first pass of two-phase dispatch, one slot each
+// (slots handed out in suspension order; capacity = the call's cell count).
+struct Suspended {
+  unsigned long long* count;  // slots used
+  int32_t* cell;              // cell index per slot
+  double *rem, *tiso;         // remaining time of the interval, isothermal T
+  int32_t *nsub, *nit;        // counters so far
+  uint32_t* fl;               // flags so far
+  int32_t* bucket;            // scratch: estimated-cost bucket per slot
+};
+
 struct Args {
   Net net;
   Par par;
@@ -58,6 +69,15 @@ struct Args {
   const Par* parc;
   const int32_t* order;         // lane work item -> cell (null: identity)
   const uint32_t* dense;        // length of the density-ordered head of order (null: 0)
+  // Two-phase dispatch.  budget > 0: a cell not done after `budget`
+  // subcycles is suspended (its state written back in place, the rest into
+  // sus) and the lane takes another cell.  resume: work items are slots of
+  // sus, taken through order, and each continues exactly where it stopped.
+  int32_t budget;
+  int32_t resume;
+  int32_t fine;                      // claim per refill only what idle lanes take, everywhere
+  const unsigned long long* limit;   // number of work items, on the device (null: c.n)
+  Suspended sus;
 };
 
 // Served form.  Requests are published by the host into a ring that lives
@@ -123,6 +143,10 @@ constexpr int kOrderWork = 2 * kOrderBuckets + 4 + 2 * kOrderBlocks;
 constexpr int kOrderDenseWord = 2 * kOrderBuckets + 1;  // plan[1]: length of the dense head
 hipError_t launch_order(const double* nh, int64_t n, int32_t* order, uint32_t* work,
                         hipStream_t s);
+// Two-phase dispatch, second phase: order[0..*sus.count) = the suspended
+// slots, longest estimated remainder first (cap = slot capacity).
+hipError_t launch_progress_order(const Suspended& sus, double dt, int32_t n_sub_max,
+                                 int64_t cap, uint32_t* work, int32_t* order, hipStream_t s);
 
 constexpr int kBlock = 256;
 

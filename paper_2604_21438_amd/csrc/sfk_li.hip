@@ -163,11 +163,11 @@ __device__ inline void k2k3(double T, double lnT, double iT, TF<R>& k2, TF<R>& k
   using M = Mth<R>;
   k2.v = M::ea(-41.11005943727161 + 0.928 * lnT - T * (1.0 / 16200.0));  // ln 1.4e-18
   k2.t = k2.v * R(0.928 * iT - 1.0 / 16200.0);
-  // N = T^a0 + c1 T^a1 + c2 T^a2 and D = 1 + c3 T^a3 + c4 T^a4 + c5 T^a5 one
-  // power at a time (kept rolled: six binary64 exponentials in flight
-  // cost registers that the whole subcycle pays for)
+  // N = T^a0 + c1 T^a1 + c2 T^a2 and D = 1 + c3 T^a3 + c4 T^a4 + c5 T^a5:
+  // the six powers are independent exponentials, unrolled so that their
+  // dependent FMA chains overlap (the kernel's register peak lies elsewhere)
   R N = R(0), dN = R(0), D = R(1), dD = R(0);
-#pragma unroll 1
+#pragma unroll
   for (int i = 0; i < 6; ++i) {
     const R p = M::ea(kH3[0][i] * lnT);
     if (i < 3) {
@@ -228,6 +228,10 @@ __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, d
   const R T = R(T64);
   const R n = R(ck.n);
   const R iT = R(iT64);
+  // every half-integer power of T below comes from one root and one
+  // reciprocal: T^1/2, T^-1/2, T^-1/4 = (T^-1/2)^1/2
+  const R sT = M::sq(T);
+  const R rsT = M::dv(R(1), sT);
 
   // ---- steady-state H- and the abundances (values in binary64) ----
   R ratio = R(0), dratio = R(0);
@@ -299,7 +303,7 @@ __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, d
     G<R> nD{R(0), R(0), R(0), R(0)};
     acc(nD, R(1.6) * n, TF<R>{e1, e1 * R(2.0 * e1x * e1x * iT64)}, YH);
     acc(nD, R(1.4) * n, TF<R>{e2, e2 * R(12000.0 * iT12 * iT12)}, Y2);
-    const R g = M::dv(R(1e6), M::sq(T));
+    const R g = R(1e6) * rsT;
     const G<R> den{nD.v + g, nD.a, nD.e, nD.t - R(0.5) * g * iT};
     f = quot(nD, den);
   }
@@ -321,8 +325,8 @@ __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, d
   }
   // H5 three-body formation, H6 = H5/8, and Gamma_1 (4.48 eV per H2)
   {
-    const R t25 = M::ea(-0.25 * lnT64);
-    const R t50 = M::ea(-0.5 * lnT64);
+    const R t50 = rsT;
+    const R t25 = M::sq(rsT);
     const TF<R> k5{R(6.0e-32) * t25 + R(2.0e-31) * t50,
                    (R(-0.25 * 6.0e-32) * t25 - R(0.5 * 2.0e-31) * t50) * iT};
     const G<R> HH = YH * YH;
@@ -359,7 +363,7 @@ __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, d
     const R D = R(1) + R(0.04) * s + R(2e-3) * T + R(8e-6) * T * T;
     const R iD = M::dv(R(1), D);
     TF<R> k8;
-    k8.v = R(nt.rm[8] * 6.0e-17) * M::sq(T * R(1.0 / 300.0)) * fa * R(ck.fd) * iD;
+    k8.v = R(nt.rm[8] * 6.0e-17 * 0.057735026918962574) * sT * fa * R(ck.fd) * iD;  // 300^-1/2
     k8.t = k8.v * (R(0.5) * iT - (R(0.02) * M::dv(R(1), s) + R(2e-3) + R(1.6e-5) * T) * iD);
     acc(rh2, n, k8, YH);
     const G<R> fc{R(0.2) + R(4.2) * f.v, R(4.2) * f.a, R(4.2) * f.e, R(4.2) * f.t};
@@ -388,7 +392,7 @@ __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, d
   }
   // Lambda_9 (H excitation, partner n(H)) and Lambda_10 (He+, all He ionised)
   {
-    const R s5 = M::sq(T * R(1e-5));
+    const R s5 = R(0.0031622776601683794) * sT;  // (T / 1e5)^1/2
     const R ds5 = R(0.5) * s5 * iT;
     const R i5 = M::dv(R(1), R(1) + s5);
     const R v9 = R(7.5e-19 / KB) * M::ea(-118348.0 * iT64) * i5;
@@ -400,7 +404,6 @@ __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, d
   // Lambda_11, free-free with the piecewise Gaunt factor
   {
     const R l = R(lnT64 * (1.0 / LN10));
-    const R sT = M::sq(T);
     R gff, dg;
     if (T64 < 3.2e5) {
       gff = R(0.79464) + R(0.1243) * l;
@@ -411,7 +414,7 @@ __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, d
     }
     acc(q, -R(nt.pm[10]) * n,
         TF<R>{R(1.426e-27 / KB) * sT * gff,
-              R(1.426e-27 / KB) * (R(0.5) * gff * M::dv(R(1), sT) + sT * dg)},
+              R(1.426e-27 / KB) * (R(0.5) * gff * rsT + sT * dg)},
         YHP * YE);
   }
   // Lambda_12, Compton cooling off the CMB
@@ -422,7 +425,7 @@ __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, d
   }
   // Lambda_13, line cooling: two-level coolants (stand-in)
   {
-    const R s100 = M::sq(R(100) * iT);
+    const R s100 = R(10) * rsT;  // (100 / T)^1/2
     G<R> ncoll = YH + Y2;
     ncoll = n * ncoll;
     G<R> nel{R(0), R(0), R(0), R(0)};
@@ -1107,6 +1110,58 @@ __device__ bool nr_attempt(const Net& nt, const Par& pr, Lane& L, double& tsub, 
 }
 
 // ------------------------------------------------------------------ I/O
+// Per-cell constants of a call, from the inputs only: the same arithmetic
+// at the first load and at a resume, so a resumed cell goes on bit for bit.
+__device__ inline void cell_consts(const Net& nt, const Par& pr, double nh, double ne, double nf,
+                                   double z, CellK& k) {
+  k.n = nh;
+  k.fd = z;
+  k.rho = (1.0 + 4.0 * pr.y_he) * MH * nh;
+  const double g0 = nf * nt.inv_g0;
+  k.k9 = nt.rm[9] * (nt.c_sigma * ne);
+  k.k10 = nt.rm[10] * (nt.k10g * g0);
+  k.k11 = nt.rm[11] * nt.zeta;
+  k.g4 = nt.pm[3] * nt.pe_k * g0 * z;  // Gamma_4 / (k_B n)
+  k.euv = nt.kap_uv_c * (nf * nt.e_fuv + ne * nt.e_euv);
+}
+
+// Two-phase dispatch: write a running cell's state back in place (its
+// y_H2, y_e, E_th, T_d [, E_IR] slots) and the rest of the lane into slot p.
+__device__ inline void suspend_cell(const Par& pr, const Cells& c, const Suspended& s, int64_t i,
+                                    unsigned long long p, const Lane& L) {
+  c.y_h2[i] = L.y2;
+  c.y_e[i] = L.ye;
+  c.eint[i] = L.E;
+  c.tdust[i] = L.Td;
+  if (pr.ir_mode == 1) c.eir[i] = L.Eir;
+  s.cell[p] = int32_t(i);
+  s.rem[p] = L.rem;
+  s.tiso[p] = L.Tiso;
+  s.nsub[p] = L.nsub;
+  s.nit[p] = L.nit;
+  s.fl[p] = L.fl;
+}
+
+// ... and take it up again: no validation and no renormalisation, the lane
+// is restored exactly as it was suspended.
+__device__ inline int64_t resume_cell(const Net& nt, const Par& pr, const Cells& c,
+                                      const Suspended& s, int32_t p, Lane& L) {
+  const int64_t i = s.cell[p];
+  L.y2 = c.y_h2[i];
+  L.ye = c.y_e[i];
+  L.E = c.eint[i];
+  L.Td = c.tdust[i];
+  const double tc2 = pr.t_cmb * pr.t_cmb;
+  L.Eir = pr.ir_mode == 1 ? c.eir[i] : ARAD * tc2 * tc2 / pr.c_red;
+  cell_consts(nt, pr, c.nh[i], c.n_euv[i], c.n_fuv[i], c.zmet ? c.zmet[i] : pr.z_default, L.ck);
+  L.rem = s.rem[p];
+  L.Tiso = s.tiso[p];
+  L.nsub = s.nsub[p];
+  L.nit = s.nit[p];
+  L.fl = s.fl[p];
+  return i;
+}
+
 // Load a cell; returns false (and writes the invalid marker) on bad input.
 template <class R>
 __device__ bool load_cell(const Net& nt, const Par& pr, const Cells& c, int64_t i, double dt,
@@ -1135,16 +1190,7 @@ __device__ bool load_cell(const Net& nt, const Par& pr, const Cells& c, int64_t 
     if (c.flags) c.flags[i] = F_INVALID;
     return false;
   }
-  CellK& k = L.ck;
-  k.n = nh;
-  k.fd = z;
-  k.rho = (1.0 + 4.0 * pr.y_he) * MH * nh;
-  const double g0 = nf * nt.inv_g0;
-  k.k9 = nt.rm[9] * (nt.c_sigma * ne);
-  k.k10 = nt.rm[10] * (nt.k10g * g0);
-  k.k11 = nt.rm[11] * nt.zeta;
-  k.g4 = nt.pm[3] * nt.pe_k * g0 * z;  // Gamma_4 / (k_B n)
-  k.euv = nt.kap_uv_c * (nf * nt.e_fuv + ne * nt.e_euv);
+  cell_consts(nt, pr, nh, ne, nf, z, L.ck);
   L.Tiso = L.E / (KB * nh * cvk(pr, L.y2, L.ye));
   L.rem = dt;
   L.nsub = 0;
@@ -1225,8 +1271,11 @@ constexpr unsigned kStash = 64;
 
 // kNR selects the Newton-Raphson comparator instead of the LI subcycle
 // (binary64 only); both share the lane refill, stash and dispatch.
+// At least two waves per SIMD for every instantiation: the NR comparator
+// would otherwise settle at one wave for a few registers over the limit.
 template <class R, bool kNR>
-__global__ __launch_bounds__(kBlock) void li_step_kernel(Args) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
+void li_step_kernel(Args) {
   const int lane = threadIdx.x & 63;
   int64_t cell = -1;
   Lane L;
@@ -1248,7 +1297,8 @@ __global__ __launch_bounds__(kBlock) void li_step_kernel(Args) {
         unsigned want = kStash;
         if (lane == leader) {
           const unsigned long long head = a.dense ? (unsigned long long)(*a.dense) : 0ull;
-          if (__hip_atomic_load(a.counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < head)
+          if (a.fine ||
+              __hip_atomic_load(a.counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < head)
             want = unsigned(nidle);
           base = atomicAdd(a.counter, (unsigned long long)want);
         }
@@ -1260,9 +1310,14 @@ __global__ __launch_bounds__(kBlock) void li_step_kernel(Args) {
         const unsigned r = lanes_below(idle);
         if (r < take) {
           const unsigned long long idx = sbase + r;
-          if (idx < (unsigned long long)a.c.n) {
-            cell = a.order ? int64_t(a.order[idx]) : int64_t(idx);
-            if (!load_cell<R>(fresh(a.netc), fresh(a.parc), a.c, cell, a.dt, L)) cell = -1;
+          const unsigned long long lim = a.limit ? *a.limit : (unsigned long long)a.c.n;
+          if (idx < lim) {
+            if (!kNR && a.resume) {
+              cell = resume_cell(fresh(a.netc), fresh(a.parc), a.c, a.sus, a.order[idx], L);
+            } else {
+              cell = a.order ? int64_t(a.order[idx]) : int64_t(idx);
+              if (!load_cell<R>(fresh(a.netc), fresh(a.parc), a.c, cell, a.dt, L)) cell = -1;
+            }
             tsub = 0.0;
             lev = 0;
             attempts = 0;
@@ -1281,6 +1336,15 @@ __global__ __launch_bounds__(kBlock) void li_step_kernel(Args) {
                             : subcycle<R>(fresh(a.netc), fresh(a.parc), L);
       if (done) {
         store_cell<R>(fresh(a.netc), fresh(a.parc), a.c, cell, L);
+        cell = -1;
+      } else if (!kNR && a.budget > 0 && L.nsub >= a.budget) {
+        // first pass over: one slot counter update per wave
+        const unsigned long long m = __ballot(true);
+        const int leader = __ffsll((long long)m) - 1;
+        unsigned long long base = 0;
+        if (lane == leader) base = atomicAdd(a.sus.count, (unsigned long long)__popcll(m));
+        base = __shfl(base, leader);
+        suspend_cell(fresh(a.parc), a.c, a.sus, cell, base + lanes_below(m), L);
         cell = -1;
       }
     }
@@ -1604,6 +1668,84 @@ __global__ __launch_bounds__(256) void order_scatter_kernel(const double* nh, in
   }
 }
 
+// Second phase of two-phase dispatch: the suspended cells, longest
+// estimated remainder first.  The estimate is the subcycles a cell still
+// needs if it keeps the average pace of its first pass, at most what the
+// subcycle cap leaves; cells go in decreasing half-octave buckets of it
+// (any order inside a bucket).  Slots [0, *count) are split into one
+// contiguous share per block.
+__device__ inline int progress_bucket(double dt, double rem, int32_t nsub, int32_t nmax) {
+  double est = double(nmax - nsub);
+  const double done = dt - rem;
+  if (done > 0.0) {
+    const double lin = double(nsub) * (rem / done);
+    if (lin < est) est = lin;
+  }
+  if (!(est > 0.0)) est = 0.0;
+  const float l2 = __builtin_amdgcn_logf(float(est) + 1.0f);  // log2
+  const int b = int(floorf(2.0f * l2));
+  return b < 0 ? 0 : (b >= kOrderBuckets ? kOrderBuckets - 1 : b);
+}
+
+__device__ inline void slot_share(unsigned long long used, int b, int nb, int64_t& begin,
+                                  int64_t& end) {
+  const int64_t per = (int64_t(used) + nb - 1) / nb;
+  begin = int64_t(b) * per;
+  end = begin + per < int64_t(used) ? begin + per : int64_t(used);
+  if (begin > end) begin = end;
+}
+
+__global__ __launch_bounds__(256) void progress_count_kernel(Suspended sus, double dt,
+                                                             int32_t nmax, uint32_t* work) {
+  __shared__ uint32_t h[kOrderBuckets];
+  for (int t = threadIdx.x; t < kOrderBuckets; t += blockDim.x) h[t] = 0u;
+  __syncthreads();
+  int64_t begin, end;
+  slot_share(*sus.count, blockIdx.x, gridDim.x, begin, end);
+  for (int64_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
+    const int b = progress_bucket(dt, sus.rem[i], sus.nsub[i], nmax);
+    sus.bucket[i] = b;
+    atomicAdd(&h[b], 1u);
+  }
+  __syncthreads();
+  const OrderWork w = order_work(work);
+  for (int t = threadIdx.x; t < kOrderBuckets; t += blockDim.x)
+    if (h[t]) atomicAdd(&w.hist[t], h[t]);
+}
+
+// One thread: bucket offsets, longest bucket first.
+__global__ void progress_plan_kernel(uint32_t* work) {
+  if (threadIdx.x != 0) return;
+  const OrderWork w = order_work(work);
+  uint32_t off = 0u;
+  for (int b = kOrderBuckets - 1; b >= 0; --b) {
+    w.offs[b] = off;
+    off += w.hist[b];
+  }
+}
+
+__global__ __launch_bounds__(256) void progress_scatter_kernel(Suspended sus, uint32_t* work,
+                                                               int32_t* order) {
+  __shared__ uint32_t cnt[kOrderBuckets], base[kOrderBuckets];
+  const OrderWork w = order_work(work);
+  int64_t begin, end;
+  slot_share(*sus.count, blockIdx.x, gridDim.x, begin, end);
+  for (int t = threadIdx.x; t < kOrderBuckets; t += blockDim.x) cnt[t] = 0u;
+  __syncthreads();
+  for (int64_t i = begin + threadIdx.x; i < end; i += blockDim.x)
+    atomicAdd(&cnt[sus.bucket[i]], 1u);
+  __syncthreads();
+  for (int t = threadIdx.x; t < kOrderBuckets; t += blockDim.x) {
+    base[t] = cnt[t] ? atomicAdd(&w.offs[t], cnt[t]) : 0u;
+    cnt[t] = 0u;
+  }
+  __syncthreads();
+  for (int64_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
+    const int b = sus.bucket[i];
+    order[base[b] + atomicAdd(&cnt[b], 1u)] = int32_t(i);
+  }
+}
+
 // Arena <-> caller copies of one request (grid-stride over its cells).
 __global__ __launch_bounds__(256) void copy_in_kernel(CopyArgs a) {
   const int64_t n = a.user.n;
@@ -1718,6 +1860,17 @@ hipError_t launch_order(const double* nh, int64_t n, int32_t* order, uint32_t* w
   hipLaunchKernelGGL(order_blockscan_kernel, dim3(1), dim3(64), 0, s, grid, work);
   hipLaunchKernelGGL(order_scatter_kernel, dim3(grid), dim3(256), 0, s, nh, n, chunk, work,
                      order);
+  return hipGetLastError();
+}
+
+hipError_t launch_progress_order(const Suspended& sus, double dt, int32_t n_sub_max,
+                                 int64_t cap, uint32_t* work, int32_t* order, hipStream_t s) {
+  const int64_t tiles = (cap + 255) / 256;
+  const int grid = int(tiles < kOrderBlocks ? (tiles > 0 ? tiles : 1) : kOrderBlocks);
+  hipLaunchKernelGGL(order_zero_kernel, dim3(1), dim3(256), 0, s, work);
+  hipLaunchKernelGGL(progress_count_kernel, dim3(grid), dim3(256), 0, s, sus, dt, n_sub_max, work);
+  hipLaunchKernelGGL(progress_plan_kernel, dim3(1), dim3(64), 0, s, work);
+  hipLaunchKernelGGL(progress_scatter_kernel, dim3(grid), dim3(256), 0, s, sus, work, order);
   return hipGetLastError();
 }
 

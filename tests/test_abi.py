@@ -58,7 +58,11 @@ def test_dispatch_default_and_validation():
     import paper_2604_21438_amd as sfc
     L = sfc.lib()
     p = sfc.default_params()
-    assert p.dispatch == sfc.DISPATCH_DENSITY
-    p.dispatch = 7
+    assert p.dispatch == sfc.DISPATCH_PROGRESS
+    assert p.phase_nsub == 4096
     h = C.c_void_p()
+    p.phase_nsub = 0
+    assert L.sfc_chem_init(None, 1.0, 1.0, C.byref(p), 0, 0, C.byref(h)) == sfc.E_INVAL
+    p.phase_nsub = 4096
+    p.dispatch = 7
     assert L.sfc_chem_init(None, 1.0, 1.0, C.byref(p), 0, 0, C.byref(h)) == sfc.E_INVAL

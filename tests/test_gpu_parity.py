@@ -217,24 +217,64 @@ def test_fp64_full_grid128_sampled():
     assert np.all(worst <= tol), np.nonzero(worst > tol)[0]
 
 
-def test_density_dispatch_changes_nothing_but_order():
-    """Lanes take the densest cells first on a launch with several cells per
-    lane; every cell is processed once and its result is bitwise the same as
-    with index order."""
-    sfc = _sfc()
-    cells, dt = W.grid128(n=400_000)
-    out = {}
-    for mode in (sfc.DISPATCH_INDEX, sfc.DISPATCH_DENSITY):
-        par = sfc.default_params(dispatch=mode)
-        out[mode] = run_gpu(cells, dt, sfc.FP64, 1.0, sfc.default_network(), par,
-                            label=f"dispatch {mode}")
-    a, b = out[sfc.DISPATCH_INDEX], out[sfc.DISPATCH_DENSITY]
-    assert np.all(b["nsub"] > 0)
-    for k in ("y_h2", "y_e", "eint", "tdust", "y_h", "y_hp", "y_hm", "tgas", "nsub", "niter",
-              "flags"):
+BITWISE_KEYS = ("y_h2", "y_e", "eint", "tdust", "y_h", "y_hp", "y_hm", "tgas", "nsub", "niter",
+                "flags")
+
+
+def _assert_bitwise(a, b, keys=BITWISE_KEYS):
+    for k in keys:
         x, y = a[k], b[k]
         same = (x.view(np.int64) == y.view(np.int64)) if x.dtype.kind == "f" else (x == y)
         assert same.all(), (k, int((~same).sum()))
+
+
+def test_dispatch_changes_nothing_but_order():
+    """Density order (densest cells first) and two-phase progress dispatch
+    (first pass of phase_nsub subcycles, then the suspended cells resumed
+    longest estimated remainder first) on a launch with several cells per
+    lane: every cell is processed once and its result is bitwise the same
+    as with index order, also when most cells are suspended and resumed."""
+    sfc = _sfc()
+    cells, dt = W.grid128(n=400_000)
+    runs = {"index": dict(dispatch=sfc.DISPATCH_INDEX),
+            "density": dict(dispatch=sfc.DISPATCH_DENSITY),
+            "progress": dict(dispatch=sfc.DISPATCH_PROGRESS),
+            "progress 64": dict(dispatch=sfc.DISPATCH_PROGRESS, phase_nsub=64)}
+    out = {}
+    for name, over in runs.items():
+        out[name] = run_gpu(cells, dt, sfc.FP64, 1.0, sfc.default_network(),
+                            sfc.default_params(**over), label=f"dispatch {name}")
+    assert np.all(out["index"]["nsub"] > 0)
+    assert np.mean(out["index"]["nsub"] > 64) > 0.5  # most cells went through a suspension
+    for name in ("density", "progress", "progress 64"):
+        _assert_bitwise(out["index"], out[name])
+
+
+def test_progress_dispatch_modes_bitwise():
+    """Suspend / resume restores the whole lane: binary32 assembly, the
+    evolved IR field, isothermal gas with frozen dust, the subcycle cap (a
+    cell suspended past n_sub_max / 2 resumes on the capped step), each
+    bitwise equal to index order with a first pass of 8 subcycles."""
+    sfc = _sfc()
+    cells, dt = W.grid128(n=131_072)
+    small, dt1 = W.small_cells()
+    rng = np.random.default_rng(5)
+    ev = {k: np.ascontiguousarray(v[:2048]) for k, v in small.items()}
+    ev["eir"] = 7.5657e-15 * (10 ** rng.uniform(np.log10(3.0), np.log10(50.0), 2048)) ** 4 / 1e-4
+    iso = {k: np.ascontiguousarray(v[:2048]) for k, v in small.items()}
+    cases = [("mixed", cells, dt, sfc.MIXED, 1.0, {}),
+             ("evolve ir", ev, dt1, sfc.FP64, 10.0, dict(ir_mode=1)),
+             ("isothermal frozen dust", iso, dt1, sfc.FP64, 1.0, dict(thermal_mode=1, dust_mode=1)),
+             ("cap 40", cells, dt, sfc.FP64, 1.0, dict(n_sub_max=40))]
+    for name, c, d, prec, fac, over in cases:
+        a = run_gpu(c, d, prec, fac, sfc.default_network(),
+                    sfc.default_params(dispatch=sfc.DISPATCH_INDEX, **over), label=f"{name} index")
+        b = run_gpu(c, d, prec, fac, sfc.default_network(),
+                    sfc.default_params(dispatch=sfc.DISPATCH_PROGRESS, phase_nsub=8, **over),
+                    label=f"{name} progress 8")
+        assert np.mean(a["nsub"] > 8) > 0.2, name
+        keys = BITWISE_KEYS + (("eir",) if "eir" in c else ())
+        _assert_bitwise(a, b, keys)
 
 
 def test_grid256_population():
