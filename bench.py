@@ -36,13 +36,13 @@ sys.path.insert(0, ROOT)
 FLOP_PER_SUBCYCLE = 1539.0
 PEAK_FP64_VALU = 78.6e12      # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 BYTES_PER_CELL = 132          # 8 float64 reads, 7 float64 writes, 3 int32 writes
-# HBM bytes of one binary64 launch on the 128^3 workload, from rocprofv3
-# --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what the
-# same counter reads for a 256 MiB device-to-device copy (bench.py
-# --calibrate-copy 256).  Valid only for the kernel source whose SHA-1 is
-# given: with any other source the figure is reported as null.
-TRAFFIC = {"kernel_sha1": "98d45df56f339f308c8b91f3a20d1f0e4cc709b4",
-           "fetch_bytes": 7.3132e8, "write_bytes": 5.5894e8}
+# HBM bytes of one binary64 step on the 128^3 workload (the two launches of
+# the LI kernel under progress dispatch, first pass and resumed pass), from
+# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled
+# by what the same counter reads for a 256 MiB device-to-device copy
+# (bench.py --calibrate-copy 256).  Valid only for the kernel source whose
+# SHA-1 is given: with any other source the figure is reported as null.
+TRAFFIC = {"kernel_sha1": None, "fetch_bytes": None, "write_bytes": None}
 KERNEL_SRC = os.path.join(ROOT, "paper_2604_21438_amd", "csrc", "sfk_li.hip")
 
 
@@ -390,7 +390,7 @@ def main():
         t1 = time.perf_counter()
         kern = [a.elapsed_time(b) * 1e-3 for a, b in evs]
         out = {k: v.cpu().numpy() for k, v in work.items()}
-        log(f"[bench] {label}: {steps} steps in {t1 - t0:.3f} s, kernel {np.mean(kern):.3f} s/launch")
+        log(f"[bench] {label}: {steps} steps in {t1 - t0:.3f} s, kernel {np.mean(kern):.3f} s/step")
         return (t1 - t0) / steps, float(np.mean(kern)), out
 
     def describe(out):
@@ -427,7 +427,7 @@ def main():
                         "log T ~ U[1,4], T_d = T, Z in {0.01,0.1,1}, dt = 10 kyr, "
                         "dust factor 1 (C_d = 1e4 erg/g/K), IR fixed",
             "cells": n, "dt_s": dt, "dust_factor": 1.0, "precision": "fp64",
-            "dispatch": "density",
+            "dispatch": "progress", "phase_nsub": int(sfc.default_params().phase_nsub),
         },
         "roofline": {
             "bound": "alu",
@@ -436,12 +436,13 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_VALU,
             "traffic": measured_traffic(),
-            "traffic_unit": "bytes per launch",
+            "traffic_unit": "bytes per step (both launches)",
             "algorithmic_bytes": n * BYTES_PER_CELL,
-            "kernel": "li_step_kernel<double>",
+            "kernel": "li_step_kernel<double, false>",
+            "launches_per_step": 2,
             "flop_per_subcycle": FLOP_PER_SUBCYCLE,
-            "subcycles_per_launch": d64["subcycles"],
-            "kernel_s_per_launch": kern_s,
+            "subcycles_per_step": d64["subcycles"],
+            "kernel_s_per_step": kern_s,
             "hbm_gbs_algorithmic": n * BYTES_PER_CELL / kern_s / 1e9,
         },
         "stats_fp64": d64,
@@ -470,7 +471,7 @@ def main():
         c = sfc.Context(dust_factor=1.0)
         s, ks, outmx = run(c, sfc.MIXED, args.steps, args.warmup, "mixed factor 1")
         c.close()
-        result["mixed"] = dict(value=n / s, ms_per_step=s * 1e3, kernel_s_per_launch=ks,
+        result["mixed"] = dict(value=n / s, ms_per_step=s * 1e3, kernel_s_per_step=ks,
                                speedup_vs_fp64=step_s / s,
                                vs_fp64={k: relerr(outmx[k], out64[k])
                                         for k in ("y_h2", "y_e", "y_h", "y_hp", "y_hm", "tgas",
