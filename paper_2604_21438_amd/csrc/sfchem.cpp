@@ -417,7 +417,11 @@ int step_launch(sfc_ctx* ctx, const sfc_cells* cells, double dt, int method, voi
   if ((density || progress) && !ensure_order(ctx, cells->n))
     return fail(ctx, SFC_E_NOMEM, std::string(who) + ": dispatch order buffer");
   if (density) {
-    const hipError_t oe = sfk::launch_order(cells->nh, cells->n, ctx->d_order, ctx->d_buckets, s);
+    // the first pass of progress dispatch orders every cell by density
+    // (cells of one density share a wave and branch alike); plain density
+    // dispatch orders the densest quarter and keeps the rest in index order
+    const hipError_t oe = sfk::launch_order(cells->nh, cells->n, progress, ctx->d_order,
+                                            ctx->d_buckets, s);
     if (oe != hipSuccess) return hip_fail(ctx, oe, "dispatch order launch");
     a.order = ctx->d_order;
     a.dense = ctx->d_buckets + sfk::kOrderDenseWord;

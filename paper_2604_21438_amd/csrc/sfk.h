@@ -134,15 +134,15 @@ int served_blocks_per_cu(int precision);
 hipError_t launch_served(const ServedArgs& a, int precision, int grid, hipStream_t s);
 hipError_t launch_copy_in(const CopyArgs& a, hipStream_t s);
 hipError_t launch_copy_out(const CopyArgs& a, hipStream_t s);
-// Density dispatch: order[0..n) = the densest quarter of the cells by
-// decreasing half-octave of n_H, then the rest in index order (n < 2^31;
-// work holds kOrderWork uint32 counters).
+// Density dispatch: order[0..n) = the densest quarter of the cells (all of
+// them with all_dense) by decreasing half-octave of n_H, then the rest in
+// index order (n < 2^31; work holds kOrderWork uint32 counters).
 constexpr int kOrderBuckets = 128;
 constexpr int kOrderBlocks = 1024;
 constexpr int kOrderWork = 2 * kOrderBuckets + 4 + 2 * kOrderBlocks;
 constexpr int kOrderDenseWord = 2 * kOrderBuckets + 1;  // plan[1]: length of the dense head
-hipError_t launch_order(const double* nh, int64_t n, int32_t* order, uint32_t* work,
-                        hipStream_t s);
+hipError_t launch_order(const double* nh, int64_t n, bool all_dense, int32_t* order,
+                        uint32_t* work, hipStream_t s);
 // Two-phase dispatch, second phase: order[0..*sus.count) = the suspended
 // slots, longest estimated remainder first (cap = slot capacity).
 hipError_t launch_progress_order(const Suspended& sus, double dt, int32_t n_sub_max,

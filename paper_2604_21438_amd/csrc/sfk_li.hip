@@ -1523,9 +1523,9 @@ __global__ __launch_bounds__(kBlock) void served_drain_kernel(ServedArgs) {
 
 // ------------------------------------------------------------------ dispatch
 // Density dispatch.  The densest cells (those in the top half-octave
-// buckets of n_H that together hold at most a quarter of the cells) go
-// first, bucket by bucket, densest first; all other cells follow in index
-// order, so that most lanes still read consecutive cells.  Each block owns
+// buckets of n_H that together hold at most a quarter of the cells, or all
+// cells) go first, bucket by bucket, densest first; all other cells follow
+// in index order, so that most lanes still read consecutive cells.  Each block owns
 // one contiguous chunk of cells.  Invalid densities (non-positive, NaN) go
 // to the lowest bucket.  Work buffer (uint32): hist[B] | offs[B] | plan[4]
 // | blockcnt[kOrderBlocks] | blockoff[kOrderBlocks].
@@ -1569,11 +1569,11 @@ __global__ __launch_bounds__(256) void order_count_kernel(const double* nh, int6
 }
 
 // One thread: the cut bucket, the dense buckets' offsets (densest first)
-// and the number of dense cells.
-__global__ void order_plan_kernel(int64_t n, uint32_t* work) {
+// and the number of dense cells; all_dense puts every cell in the head.
+__global__ void order_plan_kernel(int64_t n, int all_dense, uint32_t* work) {
   if (threadIdx.x != 0) return;
   const OrderWork w = order_work(work);
-  const uint64_t cap = uint64_t(n) / 4;
+  const uint64_t cap = all_dense ? uint64_t(n) : uint64_t(n) / 4;
   uint64_t sum = 0;
   int cut = kOrderBuckets;
   for (int b = kOrderBuckets - 1; b >= 0; --b) {
@@ -1848,14 +1848,14 @@ int copy_grid(int64_t n) {
 }
 }  // namespace
 
-hipError_t launch_order(const double* nh, int64_t n, int32_t* order, uint32_t* work,
-                        hipStream_t s) {
+hipError_t launch_order(const double* nh, int64_t n, bool all_dense, int32_t* order,
+                        uint32_t* work, hipStream_t s) {
   const int64_t tiles = (n + 255) / 256;
   const int grid = int(tiles < kOrderBlocks ? (tiles > 0 ? tiles : 1) : kOrderBlocks);
   const int64_t chunk = ((tiles + grid - 1) / grid) * 256;
   hipLaunchKernelGGL(order_zero_kernel, dim3(1), dim3(256), 0, s, work);
   hipLaunchKernelGGL(order_count_kernel, dim3(grid), dim3(256), 0, s, nh, n, chunk, work);
-  hipLaunchKernelGGL(order_plan_kernel, dim3(1), dim3(64), 0, s, n, work);
+  hipLaunchKernelGGL(order_plan_kernel, dim3(1), dim3(64), 0, s, n, int(all_dense), work);
   hipLaunchKernelGGL(order_blockcount_kernel, dim3(grid), dim3(256), 0, s, nh, n, chunk, work);
   hipLaunchKernelGGL(order_blockscan_kernel, dim3(1), dim3(64), 0, s, grid, work);
   hipLaunchKernelGGL(order_scatter_kernel, dim3(grid), dim3(256), 0, s, nh, n, chunk, work,
