@@ -42,8 +42,8 @@ BYTES_PER_CELL = 132          # 8 float64 reads, 7 float64 writes, 3 int32 write
 # by what the same counter reads for a 256 MiB device-to-device copy
 # (bench.py --calibrate-copy 256).  Valid only for the kernel source whose
 # SHA-1 is given: with any other source the figure is reported as null.
-TRAFFIC = {"kernel_sha1": "4dd6fbe6362058f38cc2c4d9626a1becf49c3724",
-           "fetch_bytes": 1.4239e9, "write_bytes": 8.1017e8}
+TRAFFIC = {"kernel_sha1": "98c374c062a3b5daef873c018abe9de42afc1238",
+           "fetch_bytes": 2.9428e9, "write_bytes": 9.0957e8}
 KERNEL_SRC = os.path.join(ROOT, "paper_2604_21438_amd", "csrc", "sfk_li.hip")
 
 
