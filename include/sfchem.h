@@ -182,7 +182,12 @@ enum {
  * binary32; LU solves, state update and renormalisation in binary64).
  * Calls on one context must not overlap (the context owns one work
  * counter); use one context per concurrent stream.
- * Errors: SFC_E_INVAL, SFC_E_DEVICE. */
+ * The call launches kernels only (no memset, no host synchronisation) and
+ * can be captured into a HIP graph, with one condition: the first call of
+ * a context with more cells than any before allocates the dispatch buffers
+ * (hipMalloc, about 40 B per cell), so make one uncaptured call of at
+ * least the captured size first.
+ * Errors: SFC_E_INVAL, SFC_E_NOMEM, SFC_E_DEVICE. */
 int sfc_chem_step(sfc_ctx* ctx, const sfc_cells* cells, double dt_seconds, int precision,
                   void* hip_stream);
 

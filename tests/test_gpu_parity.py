@@ -277,6 +277,44 @@ def test_progress_dispatch_modes_bitwise():
         _assert_bitwise(a, b, keys)
 
 
+def test_plain_step_graph_replay():
+    """The plain step (two-phase dispatch: order kernels, counter resets, two
+    LI launches) captured into a HIP graph after one eager call, replayed
+    three times with eager copies and synchronisations in between: every
+    replay is bitwise the eager result, in both precisions."""
+    import torch
+
+    sfc = _sfc()
+    cells, dt = W.grid128(n=300_000)
+    for prec in (sfc.FP64, sfc.MIXED):
+        ctx = sfc.Context(dust_factor=1.0)
+        pristine = sfc.to_device(cells, outputs=False)
+        t = sfc.to_device(cells)
+        print(f"[gpu] graph replay prec={prec}: eager", flush=True)
+        ctx.step(t, dt, prec)
+        torch.cuda.synchronize()
+        eager = {k: v.clone() for k, v in t.items()}
+        s = torch.cuda.Stream()
+        g = torch.cuda.CUDAGraph()
+        for k in ("y_h2", "y_e", "eint", "tdust"):
+            t[k].copy_(pristine[k])
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            ctx.step(t, dt, prec)
+        torch.cuda.synchronize()
+        for rep in range(3):
+            for k in ("y_h2", "y_e", "eint", "tdust"):
+                t[k].copy_(pristine[k])
+            torch.cuda.synchronize()
+            print(f"[gpu] graph replay prec={prec}: replay {rep}", flush=True)
+            g.replay()
+            torch.cuda.synchronize()
+            for k, v in eager.items():
+                assert torch.equal(t[k], v), (prec, rep, k)
+        del g
+        ctx.close()
+
+
 def test_grid256_population():
     """256^3 log-normal density with an n^-1.5 tail, 8 point sources, dust
     factor 100: binary64 parity on a seeded subsample, then the whole
