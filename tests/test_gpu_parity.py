@@ -277,6 +277,34 @@ def test_progress_dispatch_modes_bitwise():
         _assert_bitwise(a, b, keys)
 
 
+def test_progress_dispatch_edge_cases():
+    """Two-phase dispatch at the edges: one cell; a ragged count with invalid
+    cells among them (never suspended, marked as with index order); a first
+    pass of a single subcycle (every cell that needs more is suspended); a
+    first pass longer than the subcycle cap (nothing is suspended).  Each
+    bitwise equal to index order."""
+    sfc = _sfc()
+    cells, dt = W.grid128(n=4099)
+    one = {k: np.ascontiguousarray(v[:1]) for k, v in cells.items()}
+    bad = {k: np.array(v, copy=True) for k, v in cells.items()}
+    bad["nh"][::97] = -1.0
+    bad["y_h2"][5::211] = np.nan
+    bad["tdust"][7::307] = 0.0
+    cases = [("one cell", one, {}),
+             ("ragged with invalid cells, first pass 1", bad, dict(phase_nsub=1)),
+             ("first pass beyond the cap", cells, dict(phase_nsub=10_000_000, n_sub_max=5000))]
+    for name, c, over in cases:
+        idx_over = {k: v for k, v in over.items() if k != "phase_nsub"}
+        a = run_gpu(c, dt, sfc.FP64, 1.0, sfc.default_network(),
+                    sfc.default_params(dispatch=sfc.DISPATCH_INDEX, **idx_over), label=f"{name} index")
+        b = run_gpu(c, dt, sfc.FP64, 1.0, sfc.default_network(),
+                    sfc.default_params(dispatch=sfc.DISPATCH_PROGRESS, **over), label=f"{name} progress")
+        if "invalid" in name:
+            inv = (a["flags"] & sfc.F_INVALID) != 0
+            assert inv.sum() > 40 and np.all(a["nsub"][inv] == 0)
+        _assert_bitwise(a, b)
+
+
 def test_plain_step_graph_replay():
     """The plain step (two-phase dispatch: order kernels, counter resets, two
     LI launches) captured into a HIP graph after one eager call, replayed
