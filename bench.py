@@ -162,6 +162,8 @@ def served_leg(args, sfc, W, torch):
     for prec, name in ((sfc.MIXED, "served_mixed"), (sfc.FP64, "served_fp64")):
         cap = sref if prec == sfc.FP64 else served(prec, None, f"{name} all queued")
         got = snapshot()
+        if prec == sfc.MIXED:
+            mixed_ref = got
         leg = dict(all_queued=cap)
         if prec == sfc.MIXED:
             leg["vs_fp64"] = {k: relerr(got[k], ref[k]) for k in got}
@@ -173,6 +175,20 @@ def served_leg(args, sfc, W, torch):
     out["served_mixed_vs_plain_fp64_throughput"] = (out["served_mixed"]["all_queued"]["value"] /
                                                     out["plain_fp64"]["value"])
     ctx.close()
+    # admission under a budget far below the workload's arena need: requests
+    # wait for slots and memory while earlier ones drain
+    if args.served_tight_budget_mib > 0:
+        ctx = sfc.Context(dust_factor=factor,
+                          served_budget_bytes=args.served_tight_budget_mib << 20)
+        tight = served(sfc.MIXED, None,
+                       f"served_mixed all queued, budget {args.served_tight_budget_mib} MiB")
+        got = snapshot()
+        tight["budget_mib"] = args.served_tight_budget_mib
+        tight["arena_need_mib"] = total * 108 / 2 ** 20
+        tight["bitwise_equal_to_8gib_budget"] = bool(all(
+            np.array_equal(got[k].view(np.int64), mixed_ref[k].view(np.int64)) for k in got))
+        out["served_mixed_tight_budget"] = tight
+        ctx.close()
     return out
 
 
@@ -331,6 +347,8 @@ def main():
     ap.add_argument("--served-side", type=int, default=128)
     ap.add_argument("--served-budget-mib", type=int, default=8192)
     ap.add_argument("--served-load", type=float, default=0.8)
+    ap.add_argument("--served-tight-budget-mib", type=int, default=64,
+                    help="second served budget that forces queueing (0 skips it)")
     ap.add_argument("--cpu-cells", type=int, default=32768)
     ap.add_argument("--cells", type=int, default=None, help="fewer cells (testing only)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
