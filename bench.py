@@ -192,6 +192,60 @@ def served_leg(args, sfc, W, torch):
     return out
 
 
+def hii_leg(args, sfc, W, torch):
+    """LI (dust factors 1 to 1e4, C_d = 1e4 to 1e8) and the NR comparator on
+    a static H II region stand-in (n_H = 100 cm^-3 around a 40 M_sun star,
+    front at the Stromgren radius), dt = 100 yr: once as drawn (gas off its
+    thermal and ionisation balance), once after 200 kyr of the chemistry
+    alone at realistic C_d (gas near balance, as inside an H II region long
+    after the front has passed).  The ageing is preparation, not timed."""
+    cells, dt = W.hii_region(args.hii_cells)
+    n = cells["nh"].shape[0]
+    t = sfc.to_device(cells)
+    fresh = {k: t[k].clone() for k in STATE_KEYS}
+    ctx = sfc.Context(dust_factor=1.0)
+    for _ in range(20):
+        ctx.step(t, 10.0 * W.KYR, sfc.FP64)
+    torch.cuda.synchronize()
+    ctx.close()
+    aged = {k: t[k].clone() for k in STATE_KEYS}
+    out = dict(cells=n, dt_s=dt, workload="n_H = 100, S_EUV = 1.36e49 /s, R_st = 2.67 pc, 6 pc box, Z = 1")
+
+    def timed(state, run):
+        for k in STATE_KEYS:
+            t[k].copy_(state[k])
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run()
+        e1.record()
+        torch.cuda.synchronize()
+        s = e0.elapsed_time(e1) * 1e-3
+        ns = t["nsub"].cpu().numpy()
+        fl = t["flags"].cpu().numpy().view(np.uint32)
+        return dict(seconds=s, value=n / s, nsub_mean=float(ns.mean()), nsub_max=int(ns.max()),
+                    tight_fraction=float(((fl & sfc.F_TIGHT) != 0).mean()),
+                    niter_mean=float(t["niter"].cpu().numpy().mean()))
+
+    for name, state in (("fresh", fresh), ("aged_200kyr", aged)):
+        leg = {}
+        for f in (1.0, 10.0, 100.0, 1000.0, 10000.0):
+            c = sfc.Context(dust_factor=f)
+            c.step(t, dt, sfc.FP64)  # allocation and warm-up
+            leg[f"li_factor{f:g}"] = timed(state, lambda: c.step(t, dt, sfc.FP64))
+            c.close()
+        c = sfc.Context(dust_factor=1.0)
+        c.step_nr(t, dt)
+        leg["nr_factor1"] = timed(state, lambda: c.step_nr(t, dt))
+        c.close()
+        for k, v in leg.items():
+            log(f"[bench] hii {name} {k}: {v['seconds'] * 1e3:.2f} ms, nsub {v['nsub_mean']:.2f}, "
+                f"tight {v['tight_fraction']:.3f}, niter {v['niter_mean']:.2f}")
+        out[name] = leg
+    return out
+
+
 def nr_leg(args, sfc, cells, dt, torch):
     """The paper's comparison: LI (dust factor 1 and 1000) against the fully
     implicit NR solver (realistic C_d) on the first nr_cells cells of the
@@ -339,6 +393,8 @@ def main():
                     help="cells of the GMC-like hierarchy for the served leg (0 skips it)")
     ap.add_argument("--gmc-both-factors", action="store_true",
                     help="run the GMC leg at dust factor 1000 too")
+    ap.add_argument("--hii-cells", type=int, default=262144,
+                    help="cells of the H II region stand-in leg (0 skips it)")
     ap.add_argument("--nr-cells", type=int, default=262144,
                     help="cells of the LI-vs-NR comparison (0 skips it)")
     ap.add_argument("--served-requests", type=int, default=120)
@@ -502,6 +558,9 @@ def main():
         result["li_vs_nr"] = nr_leg(args, sfc, cells, dt, torch)
 
     # ---- one-zone free-fall collapse (hydro-free analogue) ----
+    if args.hii_cells > 0:
+        result["hii_stand_in"] = hii_leg(args, sfc, W, torch)
+
     if not args.no_collapse:
         result["collapse"] = collapse_leg(sfc)
 

@@ -99,6 +99,44 @@ def grid128(n: int | None = None):
     return cells, 10.0 * KYR
 
 
+PC = 3.0857e18            # parsec [cm]
+C_LIGHT = 2.99792458e10   # [cm/s]
+
+
+def hii_region(n: int = 262_144, dt_yr: float = 100.0):
+    """Static stand-in for the paper's H II region test (its hydrodynamic
+    run is out of scope): a uniform n_H = 100 cm^-3 medium around a 40 M_sun
+    star emitting S_EUV = 1.36e49 ionising photons/s, the state of the gas
+    near the time when the ionisation front has reached the Stromgren
+    radius R_st = 2.67 pc.  Cells sit at uniform positions in a 6 pc box
+    centred on the star (r >= 0.05 pc).
+      - inside the front (width 0.05 pc): ionised, T = 8000 K, T_d = 60 K;
+      - outside: neutral (y_H+ = 1e-4), T = 100 K, T_d = 20 K, turning
+        molecular over 0.3 pc beyond the front (y_H2 -> 0.5);
+      - N_EUV = S_EUV / (4 pi r^2 c), cut off past the front; N_FUV half of
+        the unattenuated value everywhere (dust attenuation neglected);
+      - n_H and T carry 5 % log-normal scatter; Z = 1.
+    dt = 100 yr stands for the step of a reduced-speed-of-light (1e-4 c)
+    radiation solver on a ~0.01 pc cell, which the paper does not state."""
+    g = _streams(5, 4)
+    x = g[0].uniform(-3.0, 3.0, (n, 3))
+    r = np.maximum(np.sqrt(np.sum(x * x, axis=1)), 0.05)
+    r_st, w = 2.67, 0.05
+    front = 1.0 / (1.0 + np.exp(np.clip((r - r_st) / w, -60.0, 60.0)))
+    nh = 100.0 * np.exp(0.05 * g[1].standard_normal(n))
+    tg = (8000.0 * front + 100.0 * (1.0 - front)) * np.exp(0.05 * g[2].standard_normal(n))
+    td = 60.0 * front + 20.0 * (1.0 - front)
+    y_hp = front * (1.0 - 1.0e-4) + (1.0 - front) * 1.0e-4
+    y_hm = np.full(n, 1.0e-12)
+    y_e = y_hp - y_hm
+    y_h2 = (1.0 - front) * 0.5 * (1.0 - np.exp(-np.maximum(r - r_st, 0.0) / 0.3))
+    y_h2 = np.maximum(np.minimum(y_h2, 0.5 * (1.0 - y_hp - y_hm) * (1.0 - 1.0e-9)), 1.0e-10)
+    flux = 1.36e49 / (4.0 * np.pi * (r * PC) ** 2 * C_LIGHT)
+    n_euv = flux * front
+    n_fuv = 0.5 * flux
+    return _pack(nh, n_euv, n_fuv, np.ones(n), y_h2, y_e, tg, td), dt_yr * YR
+
+
 def subsample(cells: dict, m: int, seed: int = 7):
     """Seeded subset of m cells (sorted indices) and the indices."""
     n = cells["nh"].shape[0]
