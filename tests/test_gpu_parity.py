@@ -75,6 +75,14 @@ def test_fp64_grid128_subsample(factor):
     _check_fp64(sub, dt, factor, label=f"grid128 subsample factor {factor}")
 
 
+def test_fp64_hii_region():
+    """The H II region stand-in (ionised gas under strong EUV, a front, a
+    photodissociated neutral shell), dt = 100 yr, at C_d = 1e4 and 1e7."""
+    cells, dt = W.hii_region(2048)
+    for factor in (1.0, 1000.0):
+        _check_fp64(cells, dt, factor, label=f"H II stand-in factor {factor:g}")
+
+
 def test_fp64_evolve_ir():
     """IR energy density evolved with the dust (Appendix C 3x3 system)."""
     cells, dt = W.small_cells()
