@@ -105,7 +105,7 @@ struct Queue {
   std::deque<Req*> inflight;           // admitted, done not yet seen; seq order
   int64_t running = 0;                 // published, done not yet seen
   hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  hipGraphExec_t exec[2] = {nullptr, nullptr};  // one per drain slot (launches of one exec serialise)
   int grid = 0;
 };
 
@@ -118,9 +118,17 @@ struct Server {
   int64_t cap = 0;
   bool evolve = false;
   Queue q[2];
-  hipStream_t copy_stream = nullptr, drain_stream = nullptr;
-  hipEvent_t drain_ev = nullptr;
-  bool drain_live = false;
+  hipStream_t copy_stream = nullptr;
+  // Two drain slots, each a CU-masked stream (its own hardware queue).  A
+  // drain kernel's waves leave once idle, but the kernel lives on while a
+  // few of them finish long cells; a second kernel launched meanwhile takes
+  // the freed slots, so newly published requests find a full complement of
+  // waves instead of the few survivors.
+  hipStream_t drain_stream[2] = {nullptr, nullptr};
+  hipEvent_t drain_ev[2] = {nullptr, nullptr};
+  bool drain_live[2] = {false, false};
+  int drain_prec[2] = {0, 0};
+  uint64_t drain_pub[2] = {0, 0};  // requests of its precision published at its launch
   int last_prec = 1;
   Ranges ranges;
 
@@ -296,28 +304,39 @@ bool step_once(Server* s) {
     s->staging.push_back(r);
     moved = true;
   }
-  // 5. keep a drain kernel running while published work is left
-  if (s->drain_live) {
-    const hipError_t e = hipEventQuery(s->drain_ev);
-    if (e == hipSuccess) s->drain_live = false;
+  // 5. keep drain kernels running while published work is left: a free
+  //    slot takes a precision that has published work and no live kernel
+  //    (alternating when both wait), else a second kernel for a precision
+  //    whose live kernel was launched before its latest publications
+  for (int i = 0; i < 2; ++i) {
+    if (!s->drain_live[i]) continue;
+    const hipError_t e = hipEventQuery(s->drain_ev[i]);
+    if (e == hipSuccess) s->drain_live[i] = false;
     else if (e != hipErrorNotReady && !hip_ok(s, e, "drain kernel")) return false;
   }
-  if (!s->drain_live) {
+  for (int i = 0; i < 2; ++i) {
+    if (s->drain_live[i]) continue;
+    const int o = 1 - i;
     int pick = -1;
-    for (int k = 1; k <= 2; ++k) {  // alternate when both precisions wait
+    for (int k = 1; k <= 2 && pick < 0; ++k) {
       const int p = (s->last_prec + k) % 2;
-      if (s->q[p].running > 0) {
-        pick = p;
-        break;
-      }
+      const bool covered = s->drain_live[o] && s->drain_prec[o] == p;
+      if (s->q[p].running > 0 && !covered) pick = p;
     }
-    if (pick >= 0) {
-      if (!hip_ok(s, hipGraphLaunch(s->q[pick].exec, s->drain_stream), "graph launch")) return false;
-      if (!hip_ok(s, hipEventRecord(s->drain_ev, s->drain_stream), "event record")) return false;
-      s->drain_live = true;
-      s->last_prec = pick;
-      moved = true;
+    if (pick < 0 && s->drain_live[o]) {
+      const int p = s->drain_prec[o];
+      const uint64_t pub = __atomic_load_n(s->q[p].published, __ATOMIC_RELAXED);
+      if (s->q[p].running > 0 && pub > s->drain_pub[o]) pick = p;
     }
+    if (pick < 0) continue;
+    Queue& q = s->q[pick];
+    if (!hip_ok(s, hipGraphLaunch(q.exec[i], s->drain_stream[i]), "graph launch")) return false;
+    if (!hip_ok(s, hipEventRecord(s->drain_ev[i], s->drain_stream[i]), "event record")) return false;
+    s->drain_live[i] = true;
+    s->drain_prec[i] = pick;
+    s->drain_pub[i] = __atomic_load_n(q.published, __ATOMIC_RELAXED);
+    s->last_prec = pick;
+    moved = true;
   }
   return moved;
 }
@@ -334,9 +353,10 @@ void run(Server* s) {
     const bool moved = step_once(s);
     std::unique_lock<std::mutex> lk(s->mu);
     const bool idle = s->outstanding == 0 && s->incoming.empty();
-    if (s->quit && idle && !s->drain_live) break;
+    const bool live = s->drain_live[0] || s->drain_live[1];
+    if (s->quit && idle && !live) break;
     if (!moved) {
-      if (idle && !s->drain_live)
+      if (idle && !live)
         s->cv_work.wait(lk, [&] { return s->quit || !s->incoming.empty(); });
       else
         s->cv_work.wait_for(lk, std::chrono::microseconds(20));
@@ -359,7 +379,8 @@ void run(Server* s) {
 
 void free_all(Server* s) {
   for (auto& q : s->q) {
-    if (q.exec) (void)hipGraphExecDestroy(q.exec);
+    for (auto& x : q.exec)
+      if (x) (void)hipGraphExecDestroy(x);
     if (q.graph) (void)hipGraphDestroy(q.graph);
     if (q.ring) (void)hipHostFree(q.ring);
     if (q.published) (void)hipHostFree(q.published);
@@ -369,9 +390,11 @@ void free_all(Server* s) {
     if (q.remaining) (void)hipFree(q.remaining);
   }
   for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
-  if (s->drain_ev) (void)hipEventDestroy(s->drain_ev);
+  for (auto& e : s->drain_ev)
+    if (e) (void)hipEventDestroy(e);
   if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
-  if (s->drain_stream) (void)hipStreamDestroy(s->drain_stream);
+  for (auto& d : s->drain_stream)
+    if (d) (void)hipStreamDestroy(d);
   if (s->arena_mem) (void)hipFree(s->arena_mem);
 }
 
@@ -440,9 +463,19 @@ Server* create(const Config& cfg, std::string* err, int* code) {
   A.flags = reinterpret_cast<uint32_t*>(inext());
   s->ranges.reset(s->cap);
 
-  if (hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking) != hipSuccess ||
-      hipStreamCreateWithFlags(&s->drain_stream, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&s->drain_ev, hipEventDisableTiming) != hipSuccess)
+  // The copy stream carries a CU mask (all CUs): a masked stream gets a
+  // hardware queue of its own.  Plain streams share the few hardware queues
+  // round-robin, and a copy kernel that lands on the drain's queue waits
+  // until the persistent drain kernel ends, so admission (copy-in) and
+  // completion (copy-out) would stall behind it.
+  std::vector<uint32_t> all_cus(size_t((cfg.cus + 31) / 32), 0u);
+  for (int c = 0; c < cfg.cus; ++c) all_cus[size_t(c / 32)] |= 1u << (c % 32);
+  const uint32_t mw = uint32_t(all_cus.size());
+  if (hipExtStreamCreateWithCUMask(&s->copy_stream, mw, all_cus.data()) != hipSuccess ||
+      hipExtStreamCreateWithCUMask(&s->drain_stream[0], mw, all_cus.data()) != hipSuccess ||
+      hipExtStreamCreateWithCUMask(&s->drain_stream[1], mw, all_cus.data()) != hipSuccess ||
+      hipEventCreateWithFlags(&s->drain_ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&s->drain_ev[1], hipEventDisableTiming) != hipSuccess)
     return fail(s, SFC_E_DEVICE, "stream/event creation");
 
   int khz = 0;
@@ -497,13 +530,14 @@ Server* create(const Config& cfg, std::string* err, int* code) {
     a.netc = cfg.netc;
     a.parc = cfg.parc;
     q.grid = cus * sfk::served_blocks_per_cu(prec);
-    if (hipStreamBeginCapture(s->drain_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    if (hipStreamBeginCapture(s->drain_stream[0], hipStreamCaptureModeThreadLocal) != hipSuccess)
       return fail(s, SFC_E_DEVICE, "graph capture");
-    const hipError_t le = sfk::launch_served(a, prec, q.grid, s->drain_stream);
-    const hipError_t ce = hipStreamEndCapture(s->drain_stream, &q.graph);
+    const hipError_t le = sfk::launch_served(a, prec, q.grid, s->drain_stream[0]);
+    const hipError_t ce = hipStreamEndCapture(s->drain_stream[0], &q.graph);
     if (le != hipSuccess || ce != hipSuccess)
       return fail(s, SFC_E_DEVICE, "graph capture of the drain kernel");
-    if (hipGraphInstantiate(&q.exec, q.graph, nullptr, nullptr, 0) != hipSuccess)
+    if (hipGraphInstantiate(&q.exec[0], q.graph, nullptr, nullptr, 0) != hipSuccess ||
+        hipGraphInstantiate(&q.exec[1], q.graph, nullptr, nullptr, 0) != hipSuccess)
       return fail(s, SFC_E_DEVICE, "graph instantiation");
   }
   if (hipDeviceSynchronize() != hipSuccess) return fail(s, SFC_E_DEVICE, "device sync");
@@ -578,7 +612,8 @@ void destroy(Server* s) {
   }
   if (s->th.joinable()) s->th.join();
   (void)hipSetDevice(s->cfg.device);
-  if (s->drain_stream) (void)hipStreamSynchronize(s->drain_stream);
+  for (auto& d : s->drain_stream)
+    if (d) (void)hipStreamSynchronize(d);
   if (s->copy_stream) (void)hipStreamSynchronize(s->copy_stream);
   for (auto& kv : s->tickets) delete kv.second;
   free_all(s);
