@@ -40,17 +40,21 @@ BYTES_PER_CELL = 132          # 8 float64 reads, 7 float64 writes, 3 int32 write
 # the LI kernel under progress dispatch, first pass and resumed pass), from
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled
 # by what the same counter reads for a 256 MiB device-to-device copy
-# (bench.py --calibrate-copy 256).  Valid only for the kernel source whose
-# SHA-1 is given: with any other source the figure is reported as null.
-TRAFFIC = {"kernel_sha1": "98c374c062a3b5daef873c018abe9de42afc1238",
-           "fetch_bytes": 2.9428e9, "write_bytes": 9.0957e8}
-KERNEL_SRC = os.path.join(ROOT, "paper_2604_21438_amd", "csrc", "sfk_li.hip")
+# (bench.py --calibrate-copy 256).  Valid only for the plain-step sources
+# whose combined SHA-1 is given (sfk.h, sfk_lane.h, sfk_li.hip, in that
+# order): with any other source the figure is reported as null.
+TRAFFIC = {"kernel_sha1": None, "fetch_bytes": None, "write_bytes": None}
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2604_21438_amd", "csrc", f)
+               for f in ("sfk.h", "sfk_lane.h", "sfk_li.hip")]
 
 
 def kernel_sha1():
     import hashlib
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha1(f.read()).hexdigest()
+    h = hashlib.sha1()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic():
@@ -343,7 +347,7 @@ def gmc_leg(args, sfc, W, torch):
                           served_budget_bytes=args.served_budget_mib << 20)
         legs = {}
         for prec, pname in ((sfc.FP64, "fp64"), (sfc.MIXED, "mixed")):
-            if prec == sfc.FP64:
+            if prec == sfc.FP64 and not args.gmc_skip_plain:
                 restore()
                 t0 = time.perf_counter()
                 for L in order:
@@ -391,6 +395,8 @@ def main():
     ap.add_argument("--no-collapse", action="store_true")
     ap.add_argument("--gmc-cells", type=int, default=1_000_000,
                     help="cells of the GMC-like hierarchy for the served leg (0 skips it)")
+    ap.add_argument("--gmc-skip-plain", action="store_true",
+                    help="GMC leg: served runs only (no plain per-level baseline)")
     ap.add_argument("--gmc-both-factors", action="store_true",
                     help="run the GMC leg at dust factor 1000 too")
     ap.add_argument("--hii-cells", type=int, default=262144,

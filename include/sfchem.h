@@ -214,7 +214,7 @@ int sfc_chem_step_nr(sfc_ctx* ctx, const sfc_cells* cells, double dt_seconds, vo
 typedef struct {
   sfc_cells cells;
   double dt_seconds;
-  int32_t level;       /* AMR level (informational)              */
+  int32_t level;       /* AMR level: claim priority (see submit)  */
   int32_t precision;   /* SFC_FP64 or SFC_MIXED                   */
   uint64_t tag;        /* caller's tag, returned in sfc_result    */
 } sfc_request;
@@ -231,7 +231,18 @@ typedef struct {
  * scheduler thread admits requests in arrival order while their state fits
  * the HBM budget, uploads them into its arena and drains all admitted work
  * with a persistent kernel replayed as a HIP graph; results are copied back
- * when a request's last block is done.
+ * when a request's last block is done.  Idle lanes take the cells of the
+ * oldest admitted request with cells left.  The waves holding cells of a
+ * finer AMR level issue first on their SIMD (level >= 5, 4, 3 above the
+ * rest): a level-L block is advanced 2^L times per coarse step, so the
+ * finest level's substeps form the longest chain of dependent requests,
+ * each as long as its slowest cell.  Results do not depend on either
+ * order.  Environment variables read when the context is created:
+ * SFC_SERVE_LEVEL_CLAIMS=1 hands out the cells of the highest level first
+ * (levels above 7 count as 7, negative ones as 0; a steady stream of fine
+ * requests then delays coarse ones without bound), SFC_SERVE_LEVEL_PRIO=0
+ * turns the issue priority off.  Up to 16384 requests per level class and
+ * precision may be in flight; admission waits beyond that.
  * Errors: SFC_E_INVAL, SFC_E_BUDGET (larger than the whole budget),
  * SFC_E_STATE (served form disabled). */
 int sfc_chem_submit(sfc_ctx* ctx, const sfc_request* req, uint64_t* ticket);

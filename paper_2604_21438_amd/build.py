@@ -17,12 +17,13 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsfchem.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["sfk_li.hip", "sfserve.cpp", "sfchem.cpp"]
+SOURCES = ["sfk_li.hip", "sfk_serve.hip", "sfserve.cpp", "sfchem.cpp"]
 # Extra device flags per source.  The LI kernels run one cell per lane for
 # thousands of loop iterations; machine LICM hoists every loop-invariant
 # binary64 constant (and products of them) out of that loop into registers,
 # which doubles the kernel's VGPR use and halves its occupancy.
-EXTRA = {"sfk_li.hip": ["-mllvm", "-disable-machine-licm"]}
+EXTRA = {"sfk_li.hip": ["-mllvm", "-disable-machine-licm"],
+         "sfk_serve.hip": ["-mllvm", "-disable-machine-licm"]}
 ARCH = os.environ.get("SFC_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",

@@ -1,7 +1,8 @@
 // sfk.h -- internal interface between the host library (sfchem.cpp) and the
-// gfx950 kernels (sfk_li.hip).  Everything here is passed by value as the
-// kernel argument block, so wave-uniform constants are read through the
-// scalar cache into SGPRs.
+// gfx950 plain-step kernels (sfk_li.hip, with the per-lane code in
+// sfk_lane.h).  Everything here is passed by value as the kernel argument
+// block, so wave-uniform constants are read through the scalar cache into
+// SGPRs.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -80,60 +81,11 @@ struct Args {
   Suspended sus;
 };
 
-// Served form.  Requests are published by the host into a ring that lives
-// in coherent pinned host memory.  Waves claim cells of the oldest request
-// with unclaimed cells: a device head index names that request, and a
-// per-slot device counter hands out its cells with one atomicAdd.  A slot
-// is reused only kRing requests later, long after every wave has moved past
-// it.  The lane that stores a request's last cell raises its done word.
-constexpr int kRing = 65536;   // ring slots
-
-struct RingEntry {            // written by the host before publication
-  uint64_t arena_off;         // first arena cell of the request
-  uint64_t n;                 // cells (> 0)
-  double dt;                  // interval [s]
-  uint64_t seq;               // request sequence number (written last)
-};
-
-struct ServedArgs {
-  Net net;
-  Par par;
-  Cells arena;                        // arena SoA arrays (n = capacity)
-  const RingEntry* ring;              // host-mapped, kRing entries
-  const uint64_t* published;          // host-mapped: requests published so far
-  unsigned long long* head;           // device: oldest request that may have unclaimed cells
-  uint32_t* claimed;                  // device, per ring slot: cells handed out
-  int32_t* remaining;                 // device, per ring slot: cells not yet stored
-  uint64_t* done;                     // host-mapped, per ring slot: seq + 1 when complete
-  uint64_t idle_ticks;                // a wave with no work for this long exits
-  uint64_t life_ticks;                // no claims after this long (wall-clock ticks)
-  uint64_t backoff_ticks;             // first wait after a claim that found nothing
-  uint64_t backoff_max_ticks;         // waits double up to this
-  int32_t refill_min;
-  const Net* netc;                    // device copies of net and par (read-only)
-  const Par* parc;
-};
-
-// Copy of one request between caller buffers and the arena.
-struct CopyArgs {
-  Cells user;        // caller buffers (n = request cells)
-  Cells arena;       // arena arrays
-  int64_t off;       // first arena cell
-  double z_default;  // zmet when the caller passes none
-  int32_t* remaining_slot;  // copy-in: set to n (may be null)
-  uint32_t* claimed_slot;   // copy-in: set to 0 (may be null)
-  int32_t ir_evolve;
-};
-
 // host-callable launchers (defined in sfk_li.hip)
 hipError_t launch_step(const Args& a, int precision, int grid, hipStream_t s);
 hipError_t launch_step_nr(const Args& a, int grid, hipStream_t s);  // binary64 NR comparator
 hipError_t launch_reset(unsigned long long* counter, hipStream_t s);
 int max_blocks_per_cu(int precision);  // 0 LI binary64, 1 LI mixed, 2 NR
-int served_blocks_per_cu(int precision);
-hipError_t launch_served(const ServedArgs& a, int precision, int grid, hipStream_t s);
-hipError_t launch_copy_in(const CopyArgs& a, hipStream_t s);
-hipError_t launch_copy_out(const CopyArgs& a, hipStream_t s);
 // Density dispatch: order[0..n) = the densest quarter of the cells (all of
 // them with all_dense) by decreasing half-octave of n_H, then the rest in
 // index order (n < 2^31; work holds kOrderWork uint32 counters).

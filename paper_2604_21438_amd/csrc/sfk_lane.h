@@ -1,0 +1,1265 @@
+// sfk_lane.h -- gfx950 per-lane device code of the linearized-implicit thermochemistry
+// update of SFUMATO# (arXiv 2604.21438).
+//
+// One lane owns one cell.  A lane keeps the whole state (y_H2, y_e, E_th,
+// T_d, E_IR, remaining time) in registers for all subcycles of its cell and
+// touches HBM only to load it and to store the result.  Cells need from one
+// to ~1e5 subcycles, so a wave does not wait for its slowest lane: lanes
+// that finish store their cell and are refilled with new cells taken from a
+// global work counter (one atomic per wave per refill, indices handed out
+// with a ballot + mbcnt prefix), until the counter passes the end.
+//
+// Per subcycle (paper sections / equations):
+//   - derived state: T_g from E_th and n_tot, y_H- = (k_H2/k_H3) y_e,
+//     y_H+ = y_e + y_H-, y_H = 1 - 2 y_H2 - y_H+ - y_H-  (conservation);
+//   - rate coefficients H0..H11 (Table "Chemical reactions") and heating /
+//     cooling 1..13 (Table "Thermal processes") with their exact partial
+//     derivatives w.r.t. (y_H2, y_e, T);
+//   - subcycle h = f_chem / max(inverse timescales)  (Eqs.
+//     timescale_of_dust, timescale_chemi, timescale_energy,
+//     timestep_subcycle); dust "tightly coupled" while the dust would need
+//     N_req >= N_cyc subcycles for the rest of the interval;
+//   - chemistry + energy: (I - h J) du = h f, u = (y_H2, y_e, E/E_ref),
+//     3x3 LU with partial pivoting in registers (Eq. eq_deq);
+//   - renormalisation to H-nuclei and charge conservation;
+//   - dust / IR / gas-grain: one Appendix C linear solve, or, when tightly
+//     coupled, backward Euler reduced to one monotone convex equation in T_d
+//     solved by Newton from the side where it is positive.
+//
+// Precision: the template parameter R is the type of the rate / source /
+// Jacobian assembly (double for SFC_FP64, float for SFC_MIXED); abundance
+// bookkeeping, the LU solves, the state update and the renormalisation are
+// always binary64.  Heating and cooling are assembled as Q / (k_B n_H) in
+// K/s so that every binary32 intermediate stays inside its normal range.
+//
+// Included by the plain step (sfk_li.hip) and the served drain
+// (sfk_serve.hip); everything here has internal linkage.
+#pragma once
+#include "sfk.h"
+
+#include <math.h>
+
+namespace sfk {
+namespace {
+
+constexpr double KB = 1.380649e-16;
+constexpr double MH = 1.67262192e-24;
+constexpr double CL = 2.99792458e10;
+constexpr double ARAD = 7.5657e-15;
+constexpr double LN10 = 2.302585092994045684;
+constexpr double RG = 5.83e-8;    // gas-grain coefficient (Appendix C)
+constexpr double THIGH = 1000.0;
+constexpr double TLOW = 75.0;
+constexpr double EVK = 1.602176634e-12 / 1.380649e-16;  // eV / k_B [K]
+
+// ------------------------------------------------------------------ math
+// 1/x for positive, finite, normal x: hardware estimate and two Newton
+// steps (within an ulp; an IEEE divide costs about twice the instructions).
+__device__ inline double frcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// sqrt(x) for positive, finite, normal x: hardware 1/sqrt estimate, one
+// coupled Newton step on (sqrt x, 1/(2 sqrt x)) and two residual
+// corrections g += (x - g^2) h (Goldschmidt's iteration, Markstein's form);
+// the library sqrt adds range scaling and special-value handling on top.
+__device__ inline double fsqrt(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+
+template <class R>
+struct Mth;
+template <>
+struct Mth<double> {
+  __device__ static double ea(double x) { return exp(x); }
+  __device__ static double ex(double x) { return exp(x); }
+  __device__ static double lg(double x) { return log(x); }
+  // every root and quotient in the assembly has a positive, normal argument
+  // (temperatures are clamped to [1, 1e8] K or floored at T_CMB)
+  __device__ static double sq(double x) { return fsqrt(x); }
+  __device__ static double dv(double a, double b) { return a * frcp(b); }
+};
+template <>
+struct Mth<float> {
+  // e^x for a binary64 argument: the range reduction x log2(e) = n + f,
+  // |f| <= 1/2, is done in binary64 so that large arguments (theta/T up to
+  // ~1e4) lose nothing; 2^f comes from the hardware v_exp_f32 (about one
+  // binary32 ulp), the result is scaled by 2^n (flushing to zero below the
+  // binary32 range).
+  __device__ static float ea(double x) {
+    const double t = x * 1.4426950408889634;
+    const double n = rint(fmax(fmin(t, 256.0), -256.0));
+    const float r = __builtin_amdgcn_exp2f(float(t - n));
+    return __builtin_amdgcn_ldexpf(r, int(n));
+  }
+  // hardware transcendental unit: v_exp_f32 / v_log_f32 are base 2
+  __device__ static float ex(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+  __device__ static float lg(float x) { return __builtin_amdgcn_logf(x) * 0.6931471805599453f; }
+  __device__ static float sq(float x) { return __builtin_amdgcn_sqrtf(x); }
+  __device__ static float dv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+};
+
+// value with partials w.r.t. (y_H2, y_e, T)
+template <class R>
+struct G {
+  R v, a, e, t;
+};
+// function of T only
+template <class R>
+struct TF {
+  R v, t;
+};
+
+template <class R>
+__device__ inline G<R> operator+(G<R> x, G<R> y) {
+  return {x.v + y.v, x.a + y.a, x.e + y.e, x.t + y.t};
+}
+template <class R>
+__device__ inline G<R> operator-(G<R> x, G<R> y) {
+  return {x.v - y.v, x.a - y.a, x.e - y.e, x.t - y.t};
+}
+template <class R>
+__device__ inline G<R> operator*(G<R> x, G<R> y) {
+  return {x.v * y.v, x.a * y.v + x.v * y.a, x.e * y.v + x.v * y.e, x.t * y.v + x.v * y.t};
+}
+template <class R>
+__device__ inline G<R> operator*(R s, G<R> x) {
+  return {s * x.v, s * x.a, s * x.e, s * x.t};
+}
+template <class R>
+__device__ inline G<R> operator*(TF<R> k, G<R> x) {
+  return {k.v * x.v, k.v * x.a, k.v * x.e, k.t * x.v + k.v * x.t};
+}
+template <class R>
+__device__ inline G<R> quot(G<R> x, G<R> y) {
+  using M = Mth<R>;
+  R iy = M::dv(R(1), y.v);
+  R q = x.v * iy;
+  return {q, (x.a - q * y.a) * iy, (x.e - q * y.e) * iy, (x.t - q * y.t) * iy};
+}
+
+// ------------------------------------------------------------------ rates
+// k_H2 (H + e -> H- + photon) and k_H3 (H- + H -> H2 + e), Table
+// "Chemical reactions"; powers of T through one shared ln T.
+// k_H3 fit: exponents a_i, coefficients c_i, and c_i a_i (for dk/dT)
+__constant__ double kH3[3][6] = {
+    {0.098493, 0.5561, 2.1826, 1.0461, 3.0424, 3.7741},
+    {1.0, 0.32852, 2.771e-7, 6.191e-3, 8.9712e-11, 3.2576e-14},
+    {0.098493, 0.32852 * 0.5561, 2.771e-7 * 2.1826, 6.191e-3 * 1.0461, 8.9712e-11 * 3.0424,
+     3.2576e-14 * 3.7741}};
+
+template <class R>
+__device__ inline void k2k3(double T, double lnT, double iT, TF<R>& k2, TF<R>& k3) {
+  using M = Mth<R>;
+  k2.v = M::ea(-41.11005943727161 + 0.928 * lnT - T * (1.0 / 16200.0));  // ln 1.4e-18
+  k2.t = k2.v * R(0.928 * iT - 1.0 / 16200.0);
+  // N = T^a0 + c1 T^a1 + c2 T^a2 and D = 1 + c3 T^a3 + c4 T^a4 + c5 T^a5:
+  // the six powers are independent exponentials, unrolled so that their
+  // dependent FMA chains overlap (the kernel's register peak lies elsewhere)
+  R N = R(0), dN = R(0), D = R(1), dD = R(0);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const R p = M::ea(kH3[0][i] * lnT);
+    if (i < 3) {
+      N = N + R(kH3[1][i]) * p;
+      dN = dN + R(kH3[2][i]) * p;
+    } else {
+      D = D + R(kH3[1][i]) * p;
+      dD = dD + R(kH3[2][i]) * p;
+    }
+  }
+  const R iN = M::dv(R(1), N), iD = M::dv(R(1), D);
+  k3.v = R(1.35e-9) * N * iD;
+  k3.t = k3.v * (dN * iN - dD * iD) * R(iT);
+}
+
+template <class R>
+struct Chem {
+  R f[3];        // R_H2, R_e [1/s], Q/(k_B n_H) [K/s]
+  R J[3][3];     // d f_i / d (y_H2, y_e, T) at fixed others
+  R ratio;       // k_H2 / k_H3 (steady-state y_H- / y_e)
+};
+
+// Per-cell constants that do not change during a call.
+struct CellK {
+  double n, fd, rho;
+  double k9, k10, k11;  // photo / CR rates
+  double g4;            // photoelectric heating / (k_B n) [K/s]
+  double euv;           // dust UV absorption [erg/g/s]
+};
+
+// A += s * (k * x), k a function of T only
+template <class R>
+__device__ inline void acc(G<R>& A, R s, TF<R> k, G<R> x) {
+  const R kv = s * k.v, kt = s * k.t;
+  A.v = A.v + kv * x.v;
+  A.a = A.a + kv * x.a;
+  A.e = A.e + kv * x.e;
+  A.t = A.t + (kt * x.v + kv * x.t);
+}
+
+// Chemistry and gas heating/cooling with partials; T_d frozen.  Each rate
+// coefficient is evaluated once and all of its contributions (reaction
+// rate and the heating / cooling it drives) are added to the three
+// accumulators at once.  Temperature, 1/T, ln T, the fit polynomials and
+// every exponent argument are binary64 in both precisions; R is the type
+// of the exponentials' results and of the products and partials.
+template <class R>
+__device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, double Td_,
+                         double Tin, const CellK& ck, Chem<R>& out) {
+  using M = Mth<R>;
+  double Tc = Tin;
+  R clampT = R(1);
+  if (Tc < 1.0) { Tc = 1.0; clampT = R(0); }
+  if (Tc > 1.0e8) { Tc = 1.0e8; clampT = R(0); }
+  const double T64 = Tc;
+  const double iT64 = frcp(Tc);
+  const double lnT64 = log(Tc);
+  const R T = R(T64);
+  const R n = R(ck.n);
+  const R iT = R(iT64);
+  // every half-integer power of T below comes from one root and one
+  // reciprocal: T^1/2, T^-1/2, T^-1/4 = (T^-1/2)^1/2
+  const R sT = M::sq(T);
+  const R rsT = M::dv(R(1), sT);
+
+  // ---- steady-state H- and the abundances (values in binary64) ----
+  R ratio = R(0), dratio = R(0);
+  TF<R> k2, k3;  // k3 is used again by Gamma_1 below
+  {
+    k2k3<R>(T64, lnT64, iT64, k2, k3);
+    k2.v *= R(nt.rm[2]);
+    k2.t *= R(nt.rm[2]);
+    if (nt.rm[3] > 0.0) {
+      const R i3 = M::dv(R(1), R(nt.rm[3]) * k3.v);
+      ratio = k2.v * i3;
+      dratio = (k2.t - ratio * R(nt.rm[3]) * k3.t) * i3;
+    }
+  }
+  out.ratio = ratio;
+  const double rd = double(ratio);
+  const double yhm_d = rd * yed;
+  const double yhp_d = yed + yhm_d;
+  const double yh_d = 1.0 - 2.0 * y2d - yhp_d - yhm_d;
+  const R ye = R(yed);
+  const G<R> Y2{R(y2d), R(1), R(0), R(0)};
+  const G<R> YE{ye, R(0), R(1), R(0)};
+  const G<R> YHM{R(yhm_d), R(0), ratio, dratio * ye};
+  const G<R> YHP{R(yhp_d), R(0), R(1) + ratio, dratio * ye};
+  const G<R> YH{R(yh_d), R(-2), R(-1) - R(2) * ratio, R(-2) * dratio * ye};
+  const G<R> HE = YH * YE;
+
+  G<R> rh2{R(0), R(0), R(0), R(0)}, re = rh2, q = rh2;
+  const R evn = R(EVK) * n;  // eV / k_B * n_H
+
+  // H2 (through the H- channel, H3): net H2 formation k_H2 n y_H y_e;
+  // Lambda_8, H- free-bound cooling k_B T k_H2 n(H) n(e)
+  acc(rh2, n, k2, HE);
+  acc(q, -R(nt.pm[7]) * n, TF<R>{T * k2.v, k2.v + T * k2.t}, HE);
+
+  // H0 collisional ionisation (fit in ln T[eV]) and Lambda_5
+  {
+    const double x = lnT64 - 9.359149794498732;  // ln(k_B / eV)
+    const double c[9] = {-32.71396786, 13.536556, -5.73932875, 1.563154998, -0.2877056,
+                         3.48255977e-2, -2.63197617e-3, 1.11954395e-4, -2.03914985e-6};
+    double P = c[8], dP = 8.0 * c[8];
+#pragma unroll
+    for (int i = 7; i >= 0; --i) P = P * x + c[i];
+#pragma unroll
+    for (int i = 7; i >= 1; --i) dP = dP * x + double(i) * c[i];
+    TF<R> k0;
+    k0.v = R(nt.rm[0]) * M::ea(P);
+    k0.t = k0.v * R(dP * iT64);
+    acc(re, n, k0, HE);
+    acc(q, -R(nt.pm[4] * 13.6) * evn, k0, HE);
+  }
+  // H1 radiative recombination
+  {
+    const R w = M::ea(0.407 * (11.654320855151537 - lnT64));  // ln 115188
+    const double L = -31.22350007575617 + 1.5 * (12.662275226919286 - lnT64) -
+                     2.242 * double(M::lg(R(1) + w));  // ln 2.753e-14, ln 315614
+    TF<R> k1;
+    k1.v = R(nt.rm[1]) * M::ea(L);
+    k1.t = k1.v * iT * (R(-1.5) + R(2.242 * 0.407) * w * M::dv(R(1), R(1) + w));
+    acc(re, -n, k1, YHP * YE);
+  }
+  // Gamma_1 factor f = (1 + n_cr/n_H)^-1 = n D / (n D + 1e6 T^-1/2)
+  G<R> f;
+  {
+    const double e1x = 400.0 * iT64;
+    const R e1 = M::ea(-e1x * e1x);
+    const double iT12 = frcp(T64 + 1200.0);
+    const R e2 = M::ea(-12000.0 * iT12);
+    G<R> nD{R(0), R(0), R(0), R(0)};
+    acc(nD, R(1.6) * n, TF<R>{e1, e1 * R(2.0 * e1x * e1x * iT64)}, YH);
+    acc(nD, R(1.4) * n, TF<R>{e2, e2 * R(12000.0 * iT12 * iT12)}, Y2);
+    const R g = R(1e6) * rsT;
+    const G<R> den{nD.v + g, nD.a, nD.e, nD.t - R(0.5) * g * iT};
+    f = quot(nD, den);
+  }
+  const R g1 = R(nt.pm[0]) * evn;  // Gamma_1 prefactor
+  // H3 in Gamma_1: 3.73 eV per H2 formed through H-
+  {
+    const TF<R> k3m{k3.v * R(nt.rm[3]), k3.t * R(nt.rm[3])};
+    acc(q, g1 * R(3.73), k3m, f * (YH * YHM));
+  }
+  const G<R> H2H = Y2 * YH;
+  const G<R> H22 = Y2 * Y2;
+  // H4 collisional dissociation by H (stand-in rate) and Lambda_6 (part)
+  {
+    TF<R> k4;
+    k4.v = R(nt.rm[4] * nt.k4_pre) * M::ea(-nt.k4_theta * iT64);
+    k4.t = k4.v * R(nt.k4_theta * iT64 * iT64);
+    acc(rh2, -n, k4, H2H);
+    acc(q, -R(nt.pm[5] * 4.48) * evn, k4, H2H);
+  }
+  // H5 three-body formation, H6 = H5/8, and Gamma_1 (4.48 eV per H2)
+  {
+    const R t50 = rsT;
+    const R t25 = M::sq(rsT);
+    const TF<R> k5{R(6.0e-32) * t25 + R(2.0e-31) * t50,
+                   (R(-0.25 * 6.0e-32) * t25 - R(0.5 * 2.0e-31) * t50) * iT};
+    const G<R> HH = YH * YH;
+    const G<R> HHH = HH * YH;
+    acc(rh2, R(nt.rm[5]) * n * n, k5, HHH);
+    acc(rh2, R(nt.rm[6] * 0.125) * n * n, k5, HH * Y2);
+    acc(q, g1 * R(4.48) * n * R(nt.rm[5]), k5, f * HHH);
+  }
+  // H7 collisional dissociation by H2: k_high^(1-a) k_low^a in ln space
+  {
+    const double lnkl = -22.860336491462885 - 6.95e4 * iT64;  // ln 1.18e-10
+    const double dlnkl = 6.95e4 * iT64 * iT64;
+    const R eb = M::ea(-6000.0 * iT64);
+    // ln(1 - e^(-6000/T)): the plain log of 1 - eb is as accurate in
+    // absolute terms (all that enters ln k) as log1p, at a third of the cost
+    const double lnkh = -16.325735015736566 - 0.5 * lnT64 - 5.2e4 * iT64 +
+                        double(M::lg(R(1) - eb));  // ln 8.125e-8
+    const double ebd = double(eb);
+    const double dlnkh = -0.5 * iT64 + 5.2e4 * iT64 * iT64 -
+                         ebd * 6000.0 * iT64 * iT64 * frcp(1.0 - ebd);
+    const double t = lnT64 * (1.0 / LN10) - 4.0;
+    const R ncr = M::ea(LN10 * (4.845 - 1.3 * t + 1.62 * t * t));
+    const double a = double(ncr * M::dv(R(1), ncr + n));
+    const double da = a * (1.0 - a) * (-1.3 + 3.24 * t) * iT64;
+    TF<R> k7;
+    k7.v = R(nt.rm[7]) * M::ea((1.0 - a) * lnkh + a * lnkl);
+    k7.t = k7.v * R((1.0 - a) * dlnkh + a * dlnkl + (lnkl - lnkh) * da);
+    acc(rh2, -n, k7, H22);
+    acc(q, -R(nt.pm[5] * 4.48) * evn, k7, H22);
+  }
+  // H8 formation on grains (T_d frozen) and Gamma_1 (0.2 + 4.2 f eV)
+  {
+    const R Td = R(Td_);
+    const R fa = M::dv(R(1), R(1) + M::ea(750.0 * (1.0 / 75.0 - 1.0 / Td_)));
+    const R s = M::sq(T + Td);
+    const R D = R(1) + R(0.04) * s + R(2e-3) * T + R(8e-6) * T * T;
+    const R iD = M::dv(R(1), D);
+    TF<R> k8;
+    k8.v = R(nt.rm[8] * 6.0e-17 * 0.057735026918962574) * sT * fa * R(ck.fd) * iD;  // 300^-1/2
+    k8.t = k8.v * (R(0.5) * iT - (R(0.02) * M::dv(R(1), s) + R(2e-3) + R(1.6e-5) * T) * iD);
+    acc(rh2, n, k8, YH);
+    const G<R> fc{R(0.2) + R(4.2) * f.v, R(4.2) * f.a, R(4.2) * f.e, R(4.2) * f.t};
+    acc(q, g1, k8, fc * YH);
+  }
+  // H9, H10, H11 (photo / cosmic-ray rates of the cell) and Gamma_2..4
+  {
+    const R k9 = R(ck.k9), k10 = R(ck.k10), k11 = R(ck.k11);
+    acc(re, k9 + k11, TF<R>{R(1), R(0)}, YH);
+    acc(rh2, -k10, TF<R>{R(1), R(0)}, Y2);
+    acc(q, R(nt.pm[1] * nt.g2k) * k9, TF<R>{R(1), R(0)}, YH);
+    acc(q, R(nt.pm[2] * nt.g3k) * k10, TF<R>{R(1), R(0)}, Y2);
+    q.v = q.v + R(ck.g4);
+  }
+  // Lambda_7, recombination cooling fit in log10 T (10^P / k_B)
+  {
+    const double l = lnT64 * (1.0 / LN10);
+    const double c[6] = {-25.87, 0.4958, -0.1052, 0.04264, -9.165e-3, 5.491e-4};
+    double P = c[5], dP = 5.0 * c[5];
+#pragma unroll
+    for (int i = 4; i >= 0; --i) P = P * l + c[i];
+#pragma unroll
+    for (int i = 4; i >= 1; --i) dP = dP * l + double(i) * c[i];
+    const R v = M::ea(LN10 * P + 36.51880780943216);  // - ln k_B
+    acc(q, -R(nt.pm[6]) * n, TF<R>{v, v * R(dP * iT64)}, YHP * YE);
+  }
+  // Lambda_9 (H excitation, partner n(H)) and Lambda_10 (He+, all He ionised)
+  {
+    const R s5 = R(0.0031622776601683794) * sT;  // (T / 1e5)^1/2
+    const R ds5 = R(0.5) * s5 * iT;
+    const R i5 = M::dv(R(1), R(1) + s5);
+    const R v9 = R(7.5e-19 / KB) * M::ea(-118348.0 * iT64) * i5;
+    acc(q, -R(nt.pm[8]) * n, TF<R>{v9, v9 * (R(118348.0 * iT64 * iT64) - ds5 * i5)}, HE);
+    const R v10 = R(5.54e-17 / KB) * M::ea(-0.397 * lnT64 - 473638.0 * iT64) * i5;
+    acc(q, -R(nt.pm[9] * pr.y_he) * n,
+        TF<R>{v10, v10 * (R(-0.397 * iT64 + 473638.0 * iT64 * iT64) - ds5 * i5)}, YE);
+  }
+  // Lambda_11, free-free with the piecewise Gaunt factor
+  {
+    const R l = R(lnT64 * (1.0 / LN10));
+    R gff, dg;
+    if (T64 < 3.2e5) {
+      gff = R(0.79464) + R(0.1243) * l;
+      dg = R(0.1243 / LN10) * iT;
+    } else {
+      gff = R(2.13164) - R(0.1240) * l;
+      dg = R(-0.1240 / LN10) * iT;
+    }
+    acc(q, -R(nt.pm[10]) * n,
+        TF<R>{R(1.426e-27 / KB) * sT * gff,
+              R(1.426e-27 / KB) * (R(0.5) * gff * rsT + sT * dg)},
+        YHP * YE);
+  }
+  // Lambda_12, Compton cooling off the CMB
+  {
+    const double tc4 = pr.t_cmb * pr.t_cmb * pr.t_cmb * pr.t_cmb;
+    const R cc = R(nt.pm[11] * 1.017e-37 * tc4 / KB);
+    acc(q, R(-1), TF<R>{R(double(cc) * (T64 - pr.t_cmb)), cc}, YE);
+  }
+  // Lambda_13, line cooling: two-level coolants (stand-in)
+  {
+    const R s100 = R(10) * rsT;  // (100 / T)^1/2
+    G<R> ncoll = YH + Y2;
+    ncoll = n * ncoll;
+    G<R> nel{R(0), R(0), R(0), R(0)};
+    acc(nel, n, TF<R>{s100, R(-0.5) * s100 * iT}, YE);
+    const R xo = R(nt.x_o * ck.fd);
+    const R m13 = -R(nt.pm[12]);
+    // kept rolled: five interleaved copies of this body cost ~130 VGPRs
+#pragma unroll 1
+    for (int j = 0; j < 5; ++j) {
+      G<R> emit;
+      if (j == 0) emit = Y2;
+      else if (j == 1) emit = G<R>{R(nt.x_c * ck.fd), R(0), R(0), R(0)};
+      else if (j == 2) emit = G<R>{xo * (R(1) - YHP.v), R(0), -xo * YHP.e, -xo * YHP.t};
+      else if (j == 3) emit = (xo * R(1.0 - nt.f_oiii)) * YHP;
+      else emit = (xo * R(nt.f_oiii)) * YHP;
+      const double tul = nt.l_tul[j];
+      const R b = M::ea(-tul * iT64);
+      const G<R> cul = R(nt.l_qn[j]) * ncoll + R(nt.l_qe[j]) * nel;
+      G<R> clu{R(0), R(0), R(0), R(0)};
+      acc(clu, R(nt.l_g[j]), TF<R>{b, b * R(tul * iT64 * iT64)}, cul);
+      G<R> den = clu + cul;
+      den.v = den.v + R(nt.l_a[j]);
+      const G<R> frac = quot(clu, den);
+      const G<R> e = emit * frac;
+      const R w = m13 * R(nt.l_tul[j] * nt.l_a[j]);
+      q.v = q.v + w * e.v;
+      q.a = q.a + w * e.a;
+      q.e = q.e + w * e.e;
+      q.t = q.t + w * e.t;
+    }
+  }
+
+  out.f[0] = rh2.v;
+  out.f[1] = re.v;
+  out.f[2] = q.v;
+  out.J[0][0] = rh2.a; out.J[0][1] = rh2.e; out.J[0][2] = rh2.t * clampT;
+  out.J[1][0] = re.a;  out.J[1][1] = re.e;  out.J[1][2] = re.t * clampT;
+  out.J[2][0] = q.a;   out.J[2][1] = q.e;   out.J[2][2] = q.t * clampT;
+}
+
+// k_H2/k_H3 alone (renormalisation and outputs)
+template <class R>
+__device__ inline double hm_ratio(const Net& nt, double Tin) {
+  using M = Mth<R>;
+  const double Tc = Tin < 1.0 ? 1.0 : (Tin > 1.0e8 ? 1.0e8 : Tin);
+  TF<R> k2, k3;
+  k2k3<R>(Tc, log(Tc), 1.0 / Tc, k2, k3);
+  const R a = R(nt.rm[2]) * k2.v, b = R(nt.rm[3]) * k3.v;
+  return b > R(0) ? double(a * M::dv(R(1), b)) : 0.0;
+}
+
+// ------------------------------------------------------------------ dust
+template <class R>
+struct Dust {
+  R G, gd, zeta, betad, absir, betair, Sd, Sir, Sg, emis, kir;
+};
+
+template <class R>
+__device__ inline void kappa(const Net& nt, R T, R& k, R& dk) {
+  using M = Mth<R>;
+  const R x = T * R(nt.kap_tn);
+  const R d = R(1) + x * x;
+  const R id = M::dv(R(1), d);
+  k = R(nt.kap_max) * x * x * id;
+  dk = R(nt.kap_max) * R(2) * x * id * id * R(nt.kap_tn);
+}
+
+// Appendix C sources and coefficients at (T_g, T_d, E_IR)
+template <class R>
+__device__ inline void dust_eval(const Net& nt, const Par& pr, double Tg_, double Td_,
+                                 double Eir_, const CellK& ck, Dust<R>& d) {
+  using M = Mth<R>;
+  const R Tg = R(Tg_), Td = R(Td_);
+  const R iTg = M::dv(R(1), Tg);
+  d.G = R(nt.pm[13] * RG * ck.n) * M::sq(Tg * R(1.0 / THIGH));
+  d.gd = R(1) - R(0.8) * M::ea(-TLOW * frcp(Tg_));
+  const R rr = Td * iTg - R(1);
+  d.zeta = R(0.5) * d.gd * rr + (d.gd - R(1)) * R(TLOW) * iTg * rr - d.gd;
+  R kd, dkd;
+  kappa<R>(nt, Td, kd, dkd);
+  d.betad = R(4) * kd + dkd * Td;
+  const R ctil = R(pr.c_red * CL);
+  if (pr.ir_mode == 1) {
+    const R E = R(Eir_);
+    const R tir = M::sq(M::sq(R(pr.c_red / ARAD) * E));
+    R ki, dki;
+    kappa<R>(nt, tir, ki, dki);
+    d.kir = ki;
+    d.absir = ki * ctil * E;
+    d.betair = ki + dki * tir * R(0.25);
+  } else {
+    const R tc = R(pr.t_cmb);
+    R ki, dki;
+    kappa<R>(nt, tc, ki, dki);
+    d.kir = ki;
+    d.absir = ki * R(CL * ARAD) * (tc * tc) * (tc * tc);
+    d.betair = ki + dki * tc * R(0.25);
+  }
+  const R td2 = Td * Td;
+  d.emis = kd * R(ARAD * CL) * td2 * td2;
+  const R coup = d.G * d.gd * (Td - Tg);
+  d.Sd = d.absir + R(ck.euv) - d.emis - coup;
+  d.Sir = R(ck.rho * ck.fd) * (d.emis - d.absir);
+  d.Sg = R(ck.fd) * coup;
+}
+
+// ------------------------------------------------------------------ LU
+// Gaussian elimination with partial pivoting (ties keep the lower row),
+// rows exchanged by selects so that everything stays in registers.
+__device__ inline void solve3(double a00, double a01, double a02, double a10, double a11,
+                              double a12, double a20, double a21, double a22, double b0,
+                              double b1, double b2, double& x0, double& x1, double& x2) {
+  // pivot column 0
+  int p = 0;
+  double best = fabs(a00);
+  if (fabs(a10) > best) { p = 1; best = fabs(a10); }
+  if (fabs(a20) > best) { p = 2; }
+  {
+    const double r0[4] = {a00, a01, a02, b0};
+    const double r1[4] = {a10, a11, a12, b1};
+    const double r2[4] = {a20, a21, a22, b2};
+    double n0[4], n1[4], n2[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      n0[j] = p == 0 ? r0[j] : (p == 1 ? r1[j] : r2[j]);
+      n1[j] = p == 1 ? r0[j] : r1[j];
+      n2[j] = p == 2 ? r0[j] : r2[j];
+    }
+    a00 = n0[0]; a01 = n0[1]; a02 = n0[2]; b0 = n0[3];
+    a10 = n1[0]; a11 = n1[1]; a12 = n1[2]; b1 = n1[3];
+    a20 = n2[0]; a21 = n2[1]; a22 = n2[2]; b2 = n2[3];
+  }
+  const double i00 = frcp(a00);
+  {
+    const double m1 = a10 * i00, m2 = a20 * i00;
+    a11 = a11 - m1 * a01; a12 = a12 - m1 * a02; b1 = b1 - m1 * b0;
+    a21 = a21 - m2 * a01; a22 = a22 - m2 * a02; b2 = b2 - m2 * b0;
+  }
+  if (fabs(a21) > fabs(a11)) {
+    double t;
+    t = a11; a11 = a21; a21 = t;
+    t = a12; a12 = a22; a22 = t;
+    t = b1; b1 = b2; b2 = t;
+  }
+  const double i11 = frcp(a11);
+  {
+    const double m = a21 * i11;
+    a22 = a22 - m * a12;
+    b2 = b2 - m * b1;
+  }
+  x2 = b2 * frcp(a22);
+  x1 = (b1 - a12 * x2) * i11;
+  x0 = (b0 - a01 * x1 - a02 * x2) * i00;
+}
+
+__device__ inline void solve2(double a00, double a01, double a10, double a11, double b0, double b1,
+                              double& x0, double& x1) {
+  if (fabs(a10) > fabs(a00)) {
+    double t;
+    t = a00; a00 = a10; a10 = t;
+    t = a01; a01 = a11; a11 = t;
+    t = b0; b0 = b1; b1 = t;
+  }
+  const double i00 = frcp(a00);
+  const double m = a10 * i00;
+  a11 = a11 - m * a01;
+  b1 = b1 - m * b0;
+  x1 = b1 * frcp(a11);
+  x0 = (b0 - a01 * x1) * i00;
+}
+
+// ------------------------------------------------------------------ lane
+struct Lane {
+  double y2, ye, E, Td, Eir, rem, Tiso;
+  CellK ck;
+  int32_t nsub, nit;
+  uint32_t fl;
+};
+
+constexpr uint32_t F_CAP = 1u, F_TIGHT = 2u, F_NOCONV = 4u, F_INVALID = 8u, F_FLOOR = 16u;
+
+__device__ inline bool finite_bits(double x) {
+  const unsigned long long b = __double_as_longlong(x);
+  return ((b >> 52) & 0x7ffull) != 0x7ffull;
+}
+
+__device__ inline double ntot_rel(const Par& pr, double y2, double ye) {
+  return 1.0 - y2 + ye + pr.y_he;
+}
+
+// E_th / (k_B n) per unit temperature: n_tot / (gamma - 1)
+__device__ inline double cvk(const Par& pr, double y2, double ye) {
+  return ntot_rel(pr, y2, ye) * pr.igm1;
+}
+
+// Conservation renormalisation (binary64): clamp the unknowns, rebuild
+// y_H from H-nuclei conservation, rescale if it went negative, floor E_th.
+template <class R>
+__device__ inline void renormalise(const Net& nt, const Par& pr, Lane& L, bool iso) {
+  if (L.y2 < 0.0) { L.y2 = 0.0; L.fl |= F_FLOOR; }
+  if (L.y2 > 0.5) { L.y2 = 0.5; L.fl |= F_FLOOR; }
+  if (L.ye < 0.0) { L.ye = 0.0; L.fl |= F_FLOOR; }
+  if (L.ye > 1.0) { L.ye = 1.0; L.fl |= F_FLOOR; }
+  const double knb = KB * L.ck.n;
+  // y_H >= 1 - 2 y_H2 - y_e - 2 r_max y_e: the exact H- ratio is only
+  // needed when this bound does not already exclude y_H < 0
+  const double yh_lo = 1.0 - 2.0 * L.y2 - L.ye - 2.0 * pr.hm_ratio_max * L.ye;
+  if (!(yh_lo >= 0.0)) {
+    const double T = iso ? L.Tiso : L.E / (knb * cvk(pr, L.y2, L.ye));
+    const double r = hm_ratio<R>(nt, T);
+    const double yhm = r * L.ye;
+    const double yhp = L.ye + yhm;
+    const double yh = 1.0 - 2.0 * L.y2 - yhp - yhm;
+    if (yh < 0.0) {
+      const double s = 1.0 / (2.0 * L.y2 + yhp + yhm);
+      L.y2 = L.y2 * s;
+      L.ye = L.ye * s;
+      L.fl |= F_FLOOR;
+    }
+  }
+  const double cv = knb * cvk(pr, L.y2, L.ye);
+  if (iso) {
+    L.E = cv * L.Tiso;
+  } else if (L.E < cv * pr.t_cmb) {
+    L.E = cv * pr.t_cmb;
+    L.fl |= F_FLOOR;
+  }
+}
+
+// kappa in binary64 for the tight Newton
+__device__ inline void kappa_d(const Net& nt, double T, double& k, double& dk) {
+  const double x = T * nt.kap_tn;
+  const double id = frcp(1.0 + x * x);
+  k = nt.kap_max * x * x * id;
+  dk = nt.kap_max * 2.0 * x * (id * id) * nt.kap_tn;
+}
+
+struct TightC {
+  double td0, tg0, e0, h, ggd, dg, P, iqd, absfix, kir, euv, cd;  // iqd = 1 / q_d
+};
+
+__device__ inline void tight_phi(const Net& nt, const Par& pr, const TightC& t, double x,
+                                 double& phi, double& dphi) {
+  const double ac = ARAD * CL;
+  const double ctil = pr.c_red * CL;
+  double k, dk;
+  kappa_d(nt, x, k, dk);
+  const double x3 = x * x * x;
+  const double emis = k * ac * x3 * x;
+  const double demis = ac * x3 * (4.0 * k + dk * x);
+  double ab, dab;
+  if (pr.ir_mode == 1) {
+    const double E = (t.e0 + t.P * emis) * t.iqd;
+    ab = t.kir * ctil * E;
+    dab = t.kir * ctil * t.P * demis * t.iqd;
+  } else {
+    ab = t.absfix;
+    dab = 0.0;
+  }
+  phi = t.cd * (x - t.td0) - t.h * (ab + t.euv - emis - t.ggd * t.dg * (x - t.tg0));
+  dphi = t.cd - t.h * (dab - demis - t.ggd * t.dg);
+}
+
+// Tight gas-dust coupling: backward Euler over h with G, gamma_d and
+// kappa(T_IR) frozen; T_g and E_IR are explicit in T_d, leaving one
+// increasing convex equation Phi(T_d) = 0.
+template <class R>
+__device__ inline void dust_tight(const Net& nt, const Par& pr, Lane& L, double h) {
+  const double knb = KB * L.ck.n;
+  const double cv = knb * cvk(pr, L.y2, L.ye);
+  const double Tg0 = L.E * frcp(cv);
+  Dust<R> d;
+  dust_eval<R>(nt, pr, Tg0, L.Td, L.Eir, L.ck, d);
+  TightC t;
+  t.td0 = L.Td;
+  t.tg0 = Tg0;
+  t.e0 = L.Eir;
+  t.h = h;
+  t.cd = pr.cd;
+  t.euv = L.ck.euv;
+  const double alpha = cv * frcp(L.ck.rho);
+  t.ggd = double(d.G) * double(d.gd);
+  const double w = h * L.ck.fd * t.ggd;
+  const double iaw = frcp(alpha + w);
+  t.dg = alpha * iaw;
+  t.P = h * L.ck.rho * L.ck.fd;
+  t.kir = double(d.kir);
+  t.iqd = frcp(1.0 + t.P * pr.c_red * CL * t.kir);
+  t.absfix = double(d.absir);
+
+  double lo = pr.t_cmb, hi, f, fp, x;
+  int it = 0;
+  bool conv = true;
+  tight_phi(nt, pr, t, lo, f, fp);
+  if (f >= 0.0) {
+    x = lo;
+    L.fl |= F_FLOOR;
+  } else {
+    hi = fmax(fmax(t.td0, t.tg0), lo);
+    tight_phi(nt, pr, t, hi, f, fp);
+    for (int guard = 0; f <= 0.0 && guard < 200; ++guard) {
+      lo = hi;
+      hi = hi * 2.0;
+      tight_phi(nt, pr, t, hi, f, fp);
+    }
+    x = t.td0;
+    if (!(x > lo && x <= hi)) x = hi;
+    conv = false;
+    for (it = 1; it <= pr.newton_max; ++it) {
+      tight_phi(nt, pr, t, x, f, fp);
+      if (f == 0.0) { conv = true; break; }
+      double xn = x - f * frcp(fp);  // Phi' >= C_d > 0
+      if (f < 0.0) {
+        lo = x;
+        if (!(xn < hi)) xn = hi;
+      } else {
+        hi = x;
+        if (!(xn > lo)) xn = 0.5 * (lo + hi);
+      }
+      const double dx = xn - x;
+      x = xn;
+      if (fabs(dx) <= pr.newton_rtol * x) {
+        tight_phi(nt, pr, t, x, f, fp);
+        xn = x - f * frcp(fp);
+        if (xn >= lo && xn <= hi) x = xn;
+        conv = true;
+        break;
+      }
+    }
+    if (it > pr.newton_max) it = pr.newton_max;
+  }
+  if (!conv) L.fl |= F_NOCONV;
+  L.nit += it;
+  const double tg = (alpha * t.tg0 + w * x) * iaw;
+  if (pr.ir_mode == 1) {
+    double k, dk;
+    kappa_d(nt, x, k, dk);
+    L.Eir = (t.e0 + t.P * k * ARAD * CL * x * x * x * x) * t.iqd;
+  }
+  L.Td = x;
+  L.E = L.E + cv * (tg - Tg0);
+}
+
+// One Appendix C linear solve over h, rows and columns scaled.
+template <class R>
+__device__ inline void dust_linear(const Net& nt, const Par& pr, Lane& L, double h) {
+  const double knb = KB * L.ck.n;
+  const double cv = knb * cvk(pr, L.y2, L.ye);
+  const double Tg = L.E * frcp(cv);
+  Dust<R> d;
+  dust_eval<R>(nt, pr, Tg, L.Td, L.Eir, L.ck, d);
+  const double ctil = pr.c_red * CL;
+  const double ac = ARAD * CL;
+  const double G = double(d.G), gd = double(d.gd), zeta = double(d.zeta);
+  const double betad = double(d.betad), betair = double(d.betair);
+  const double alpha = cv * frcp(L.ck.rho);
+  const double td3 = L.Td * L.Td * L.Td;
+  const double rho = L.ck.rho, fd = L.ck.fd, cd = pr.cd;
+  const double A00 = cd + h * G * gd + h * ac * td3 * betad;
+  const double A02 = h * G * zeta;
+  const double A20 = -(h * fd * G * gd);
+  const double A22 = alpha - h * fd * G * zeta;
+  const double b0 = h * double(d.Sd);
+  const double b2 = h * double(d.Sg);
+  const double s0 = cd * L.Td, s2 = alpha * Tg;  // row scales
+  if (pr.ir_mode == 1) {
+    const double A01 = -(h * ctil * betair);
+    const double A10 = -(rho * h * ac * td3 * fd * betad);
+    const double A11 = 1.0 + rho * h * ctil * fd * betair;
+    const double b1 = h * double(d.Sir);
+    const double E = L.Eir;
+    double x0, x1, x2;
+    const double i0 = frcp(s0), i1 = frcp(E), i2 = frcp(s2);
+    solve3(A00 * L.Td * i0, A01 * E * i0, A02 * Tg * i0,
+           A10 * L.Td * i1, A11, 0.0,
+           A20 * L.Td * i2, 0.0, A22 * Tg * i2,
+           b0 * i0, b1 * i1, b2 * i2, x0, x1, x2);
+    L.Td = L.Td + x0 * L.Td;
+    L.Eir = L.Eir + x1 * E;
+    L.E = L.E + cv * (x2 * Tg);
+  } else {
+    double x0, x1;
+    const double i0 = frcp(s0), i2 = frcp(s2);
+    solve2(A00 * L.Td * i0, A02 * Tg * i0, A20 * L.Td * i2, A22 * Tg * i2, b0 * i0, b2 * i2,
+           x0, x1);
+    L.Td = L.Td + x0 * L.Td;
+    L.E = L.E + cv * (x1 * Tg);
+  }
+}
+
+__device__ inline void dust_floors(const Par& pr, Lane& L) {
+  if (L.Td < pr.t_cmb) { L.Td = pr.t_cmb; L.fl |= F_FLOOR; }
+  const double cv = KB * L.ck.n * cvk(pr, L.y2, L.ye);
+  if (L.E < cv * pr.t_cmb) { L.E = cv * pr.t_cmb; L.fl |= F_FLOOR; }
+  if (pr.ir_mode == 1) {
+    const double tc2 = pr.t_cmb * pr.t_cmb;
+    const double emin = ARAD * tc2 * tc2 / pr.c_red;
+    if (L.Eir < emin) { L.Eir = emin; L.fl |= F_FLOOR; }
+  }
+}
+
+// One subcycle; returns true when the cell has covered its interval.
+template <class R>
+__device__ bool subcycle(const Net& nt, const Par& pr, Lane& L) {
+  const bool iso = pr.thermal_mode == 1;
+  const bool dust_on = (pr.dust_mode == 0) && !iso;
+  const double knb = KB * L.ck.n;
+  const double ntr = ntot_rel(pr, L.y2, L.ye);
+  const double Ek = L.E * frcp(knb);            // E_th / (k_B n) [K]
+  const double intr = frcp(ntr);
+  const double T = iso ? L.Tiso : Ek * pr.gm1 * intr;
+
+  Chem<R> ch;
+  assemble<R>(nt, pr, L.y2, L.ye, L.Td, T, L.ck, ch);
+  const double f0 = double(ch.f[0]), f1 = double(ch.f[1]), fq = double(ch.f[2]);
+
+  double nu_dust = 0.0, qgg = 0.0;
+  if (dust_on) {
+    Dust<R> d;
+    dust_eval<R>(nt, pr, T, L.Td, L.Eir, L.ck, d);
+    // gas-grain exchange rho S_g / (k_B n) [K/s]
+    qgg = double(d.Sg) * (L.ck.rho / knb);
+    const double alpha = knb * (ntr * pr.igm1) * frcp(L.ck.rho);
+    nu_dust = fabs(double(d.Sd)) * frcp(pr.cd * L.Td);
+    nu_dust = fmax(nu_dust, fabs(double(d.Sg)) * frcp(alpha * T));
+    if (pr.ir_mode == 1) nu_dust = fmax(nu_dust, fabs(double(d.Sir)) * frcp(L.Eir));
+  }
+  const bool tight = dust_on && (L.rem * nu_dust / pr.f_chem >= double(pr.n_cyc));
+  if (tight) L.fl |= F_TIGHT;
+
+  const double iEk = frcp(Ek);
+  double nu = fmax(fabs(f0) * frcp(fmax(L.y2, pr.y_abs)), fabs(f1) * frcp(fmax(L.ye, pr.y_abs)));
+  if (!iso) nu = fmax(nu, fabs(fq + qgg) * iEk);
+  if (!tight) nu = fmax(nu, nu_dust);
+
+  double h;
+  bool last = false;
+  // below 1e-300 the step is far beyond any interval: take the rest
+  h = nu > 1e-300 ? pr.f_chem * frcp(nu) : L.rem;
+  if (h >= L.rem) {
+    h = L.rem;
+    last = true;
+  } else if (L.nsub >= pr.n_sub_max / 2) {
+    const double hcap = L.rem / double(pr.n_sub_max - L.nsub);
+    if (h < hcap) {
+      h = hcap;
+      L.fl |= F_CAP;
+      if (h >= L.rem) { h = L.rem; last = true; }
+    }
+  }
+
+  // chemistry + energy: (I - h J) du = h f, u = (y_H2, y_e, E/E_ref)
+  {
+    const double Tn = T * intr;
+    const double dTy2 = iso ? 0.0 : Tn;
+    const double dTye = iso ? 0.0 : -Tn;
+    const double dTu = iso ? 0.0 : T;
+    double J00 = double(ch.J[0][0]) + double(ch.J[0][2]) * dTy2;
+    double J01 = double(ch.J[0][1]) + double(ch.J[0][2]) * dTye;
+    double J02 = double(ch.J[0][2]) * dTu;
+    double J10 = double(ch.J[1][0]) + double(ch.J[1][2]) * dTy2;
+    double J11 = double(ch.J[1][1]) + double(ch.J[1][2]) * dTye;
+    double J12 = double(ch.J[1][2]) * dTu;
+    double J20 = 0.0, J21 = 0.0, J22 = 0.0, g2 = 0.0;
+    if (!iso) {
+      g2 = fq * iEk;
+      J20 = (double(ch.J[2][0]) + double(ch.J[2][2]) * dTy2) * iEk;
+      J21 = (double(ch.J[2][1]) + double(ch.J[2][2]) * dTye) * iEk;
+      J22 = double(ch.J[2][2]) * dTu * iEk;
+    }
+    double x0, x1, x2;
+    solve3(1.0 - h * J00, -(h * J01), -(h * J02), -(h * J10), 1.0 - h * J11, -(h * J12),
+           -(h * J20), -(h * J21), 1.0 - h * J22, h * f0, h * f1, h * g2, x0, x1, x2);
+    const double Eref = L.E;
+    L.y2 = L.y2 + x0;
+    L.ye = L.ye + x1;
+    if (!iso) L.E = L.E + x2 * Eref;
+  }
+  renormalise<R>(nt, pr, L, iso);
+
+  if (dust_on) {
+    if (!tight) dust_linear<R>(nt, pr, L, h);
+    else dust_tight<R>(nt, pr, L, h);
+    dust_floors(pr, L);
+  }
+  L.nsub += 1;
+  if (!last) L.rem = L.rem - h;
+  return last;
+}
+
+// ------------------------------------------------------------------ NR
+// Fully implicit Newton-Raphson comparator (Sec. 2, the iterative scheme
+// the LI method replaces; binary64 only).  Backward Euler over a substep
+// dts for (y_H2, y_e, T_g, T_d, E_IR), solved as three nested groups: the
+// outer Newton iteration on T_g (derivative of the energy residual by a
+// central difference, step 1e-4 T_g), and at each trial T_g the dust/IR
+// group and then the chemistry group.  Tolerance 1e-5 relative, relaxed to
+// 1e-3 after half of the 20 allowed outer iterations; every loop gives up
+// after 20 iterations, and a failed substep is halved (Eq. substep_NRchem).
+// Energies are carried per k_B n_H [K], as in the LI kernel.
+struct NRState {
+  double y2, ye, T, Td, Eir;
+};
+
+// group (ii): (T_d, E_IR) at fixed T_g
+__device__ inline bool nr_dust(const Net& nt, const Par& pr, const CellK& ck, double Td0,
+                               double Eir0, double dts, double T, double tol, double& Td,
+                               double& Eir, int32_t& its) {
+  const double ctil = pr.c_red * CL;
+  const double ac = ARAD * CL;
+  for (int it = 1; it <= 20; ++it) {
+    ++its;
+    Dust<double> d;
+    dust_eval<double>(nt, pr, T, Td, Eir, ck, d);
+    const double td3 = Td * Td * Td;
+    const double F1 = pr.cd * (Td - Td0) - dts * d.Sd;
+    const double J11 = pr.cd + dts * (ac * td3 * d.betad + d.G * d.gd);
+    double dTd, dE = 0.0;
+    if (pr.ir_mode == 1) {
+      const double F2 = Eir - Eir0 - dts * d.Sir;
+      const double J12 = -(dts * ctil * d.betair);
+      const double J21 = -(dts * ck.rho * ck.fd * ac * td3 * d.betad);
+      const double J22 = 1.0 + dts * ck.rho * ck.fd * ctil * d.betair;
+      const double det = J11 * J22 - J12 * J21;
+      dTd = -(F1 * J22 - J12 * F2) / det;
+      dE = -(J11 * F2 - J21 * F1) / det;
+    } else {
+      dTd = -F1 / J11;
+    }
+    double Tn = Td + dTd;
+    bool ok = fabs(dTd) <= tol * fabs(Tn);
+    if (Tn < 0.5 * Td) { Tn = 0.5 * Td; ok = false; }
+    if (Tn > 2.0 * Td) { Tn = 2.0 * Td; ok = false; }
+    double En = Eir;
+    if (pr.ir_mode == 1) {
+      En = Eir + dE;
+      ok = ok && fabs(dE) <= tol * fabs(En);
+      if (En < 0.5 * Eir) { En = 0.5 * Eir; ok = false; }
+      if (En > 2.0 * Eir) { En = 2.0 * Eir; ok = false; }
+    }
+    Td = Tn;
+    Eir = En;
+    if (ok) return true;
+  }
+  return false;
+}
+
+// group (iii): (y_H2, y_e) at fixed T_g, T_d; steps that would leave the
+// bounds are damped towards them
+__device__ inline bool nr_chem(const Net& nt, const Par& pr, const CellK& ck, double y20,
+                               double ye0, double dts, double T, double Td, double tol,
+                               double& y2, double& ye, int32_t& its) {
+  for (int it = 1; it <= 20; ++it) {
+    ++its;
+    Chem<double> ch;
+    assemble<double>(nt, pr, y2, ye, Td, T, ck, ch);
+    const double F1 = y2 - y20 - dts * ch.f[0];
+    const double F2 = ye - ye0 - dts * ch.f[1];
+    const double J11 = 1.0 - dts * ch.J[0][0], J12 = -(dts * ch.J[0][1]);
+    const double J21 = -(dts * ch.J[1][0]), J22 = 1.0 - dts * ch.J[1][1];
+    const double det = J11 * J22 - J12 * J21;
+    const double d1 = -(F1 * J22 - J12 * F2) / det;
+    const double d2 = -(J11 * F2 - J21 * F1) / det;
+    double n1 = y2 + d1, n2 = ye + d2;
+    bool ok = fabs(d1) <= tol * fmax(fabs(n1), pr.y_abs) &&
+              fabs(d2) <= tol * fmax(fabs(n2), pr.y_abs);
+    if (n1 < 0.0) { n1 = 0.1 * y2; ok = false; }
+    if (n1 > 0.5) { n1 = 0.5 * (y2 + 0.5); ok = false; }
+    if (n2 < 0.0) { n2 = 0.1 * ye; ok = false; }
+    if (n2 > 1.0) { n2 = 0.5 * (ye + 1.0); ok = false; }
+    y2 = n1;
+    ye = n2;
+    if (ok) return true;
+  }
+  return false;
+}
+
+// inner groups at trial T; G = residual of the gas energy equation / (k_B n)
+__device__ inline bool nr_inner(const Net& nt, const Par& pr, const CellK& ck, const Lane& s0,
+                                double dts, double T, double tol, bool dust_on, NRState& g,
+                                double& G, int32_t& its) {
+  if (dust_on && !nr_dust(nt, pr, ck, s0.Td, s0.Eir, dts, T, tol, g.Td, g.Eir, its)) return false;
+  if (!nr_chem(nt, pr, ck, s0.y2, s0.ye, dts, T, g.Td, tol, g.y2, g.ye, its)) return false;
+  Chem<double> ch;
+  assemble<double>(nt, pr, g.y2, g.ye, g.Td, T, ck, ch);
+  const double knb = KB * ck.n;
+  double gas_grain = 0.0;
+  if (dust_on) {
+    Dust<double> d;
+    dust_eval<double>(nt, pr, T, g.Td, g.Eir, ck, d);
+    gas_grain = d.Sg * (ck.rho / knb);
+  }
+  G = cvk(pr, g.y2, g.ye) * T - s0.E / knb - dts * (ch.f[2] + gas_grain);
+  return true;
+}
+
+// One backward-Euler substep of length dts from L; on success L holds the
+// new state.  Outer iterations are counted in L.nit.
+__device__ bool nr_substep(const Net& nt, const Par& pr, Lane& L, double dts) {
+  const bool iso = pr.thermal_mode == 1;
+  const bool dust_on = (pr.dust_mode == 0) && !iso;
+  const double knb = KB * L.ck.n;
+  const Lane s0 = L;
+  NRState g{L.y2, L.ye, iso ? L.Tiso : L.E / (knb * cvk(pr, L.y2, L.ye)), L.Td, L.Eir};
+  int32_t its = 0;
+  if (iso) {
+    double Gv;
+    if (!nr_inner(nt, pr, L.ck, s0, dts, L.Tiso, 1e-5, dust_on, g, Gv, its)) return false;
+    L.y2 = g.y2;
+    L.ye = g.ye;
+    L.Td = g.Td;
+    L.Eir = g.Eir;
+    L.E = knb * cvk(pr, L.y2, L.ye) * L.Tiso;
+    L.nit += 1;
+    return true;
+  }
+  double tol = 1e-5;
+  for (int it = 1; it <= 20; ++it) {
+    L.nit += 1;
+    if (it > 10) tol = 1e-3;
+    const double T = g.T;
+    const double dl = 1e-4 * T;
+    NRState gm = g, gc = g, gp = g;
+    double Gm, Gc, Gp;
+    if (!nr_inner(nt, pr, L.ck, s0, dts, T - dl, tol, dust_on, gm, Gm, its)) return false;
+    if (!nr_inner(nt, pr, L.ck, s0, dts, T, tol, dust_on, gc, Gc, its)) return false;
+    if (!nr_inner(nt, pr, L.ck, s0, dts, T + dl, tol, dust_on, gp, Gp, its)) return false;
+    const double dG = (Gp - Gm) / (2.0 * dl);
+    double Tn = T - Gc / dG;
+    bool limited = false;
+    if (!(Tn > 0.5 * T)) { Tn = 0.5 * T; limited = true; }
+    if (!(Tn < 2.0 * T)) { Tn = 2.0 * T; limited = true; }
+    if (Tn < pr.t_cmb) { Tn = pr.t_cmb; limited = true; }
+    const bool ok = !limited && fabs(Tn - T) <= tol * Tn &&
+                    fabs(gc.y2 - g.y2) <= tol * fmax(gc.y2, pr.y_abs) &&
+                    fabs(gc.ye - g.ye) <= tol * fmax(gc.ye, pr.y_abs) &&
+                    fabs(gc.Td - g.Td) <= tol * gc.Td;
+    g = gc;
+    g.T = Tn;
+    if (ok) {
+      double Gv;
+      if (!nr_inner(nt, pr, L.ck, s0, dts, Tn, tol, dust_on, g, Gv, its)) return false;
+      L.y2 = g.y2;
+      L.ye = g.ye;
+      L.Td = g.Td;
+      L.Eir = g.Eir;
+      L.E = knb * cvk(pr, L.y2, L.ye) * Tn;
+      return true;
+    }
+  }
+  return false;
+}
+
+constexpr uint32_t F_NRFAIL = 32u;
+
+// One substep attempt of the NR driver (Eq. substep_NRchem): the first
+// try covers the whole interval; dts = (dt - t_sub) / 2^lev, lev + 1 on
+// failure, max(lev - 1, 0) on success.  L.rem holds dt, tsub and lev the
+// driver state.  At most n_sub_max attempts (then NRFAIL), so every cell
+// ends.  Returns true when the cell is done.
+__device__ bool nr_attempt(const Net& nt, const Par& pr, Lane& L, double& tsub, int& lev,
+                           int& attempts) {
+  const double dts = (L.rem - tsub) / ldexp(1.0, lev);
+  Lane trial = L;
+  const bool ok = nr_substep(nt, pr, trial, dts);
+  L.nit = trial.nit;
+  ++attempts;
+  if (ok) {
+    const int32_t nit = L.nit;
+    L = trial;
+    L.nit = nit;
+    L.nsub += 1;
+    if (lev == 0) return true;
+    tsub = tsub + dts;
+    lev = lev > 0 ? lev - 1 : 0;
+  } else {
+    ++lev;
+    if (lev > 60) { L.fl |= F_NRFAIL; return true; }
+  }
+  if (attempts >= pr.n_sub_max) { L.fl |= F_NRFAIL; return true; }
+  return false;
+}
+
+// ------------------------------------------------------------------ I/O
+// Per-cell constants of a call, from the inputs only: the same arithmetic
+// at the first load and at a resume, so a resumed cell goes on bit for bit.
+__device__ inline void cell_consts(const Net& nt, const Par& pr, double nh, double ne, double nf,
+                                   double z, CellK& k) {
+  k.n = nh;
+  k.fd = z;
+  k.rho = (1.0 + 4.0 * pr.y_he) * MH * nh;
+  const double g0 = nf * nt.inv_g0;
+  k.k9 = nt.rm[9] * (nt.c_sigma * ne);
+  k.k10 = nt.rm[10] * (nt.k10g * g0);
+  k.k11 = nt.rm[11] * nt.zeta;
+  k.g4 = nt.pm[3] * nt.pe_k * g0 * z;  // Gamma_4 / (k_B n)
+  k.euv = nt.kap_uv_c * (nf * nt.e_fuv + ne * nt.e_euv);
+}
+
+// Two-phase dispatch: write a running cell's state back in place (its
+// y_H2, y_e, E_th, T_d [, E_IR] slots) and the rest of the lane into slot p.
+__device__ inline void suspend_cell(const Par& pr, const Cells& c, const Suspended& s, int64_t i,
+                                    unsigned long long p, const Lane& L) {
+  c.y_h2[i] = L.y2;
+  c.y_e[i] = L.ye;
+  c.eint[i] = L.E;
+  c.tdust[i] = L.Td;
+  if (pr.ir_mode == 1) c.eir[i] = L.Eir;
+  s.cell[p] = int32_t(i);
+  s.rem[p] = L.rem;
+  s.tiso[p] = L.Tiso;
+  s.nsub[p] = L.nsub;
+  s.nit[p] = L.nit;
+  s.fl[p] = L.fl;
+}
+
+// ... and take it up again: no validation and no renormalisation, the lane
+// is restored exactly as it was suspended.
+__device__ inline int64_t resume_cell(const Net& nt, const Par& pr, const Cells& c,
+                                      const Suspended& s, int32_t p, Lane& L) {
+  const int64_t i = s.cell[p];
+  L.y2 = c.y_h2[i];
+  L.ye = c.y_e[i];
+  L.E = c.eint[i];
+  L.Td = c.tdust[i];
+  const double tc2 = pr.t_cmb * pr.t_cmb;
+  L.Eir = pr.ir_mode == 1 ? c.eir[i] : ARAD * tc2 * tc2 / pr.c_red;
+  cell_consts(nt, pr, c.nh[i], c.n_euv[i], c.n_fuv[i], c.zmet ? c.zmet[i] : pr.z_default, L.ck);
+  L.rem = s.rem[p];
+  L.Tiso = s.tiso[p];
+  L.nsub = s.nsub[p];
+  L.nit = s.nit[p];
+  L.fl = s.fl[p];
+  return i;
+}
+
+// Load a cell; returns false (and writes the invalid marker) on bad input.
+template <class R>
+__device__ bool load_cell(const Net& nt, const Par& pr, const Cells& c, int64_t i, double dt,
+                          Lane& L) {
+  const double nh = c.nh[i], ne = c.n_euv[i], nf = c.n_fuv[i];
+  const double z = c.zmet ? c.zmet[i] : pr.z_default;
+  L.y2 = c.y_h2[i];
+  L.ye = c.y_e[i];
+  L.E = c.eint[i];
+  L.Td = c.tdust[i];
+  const double tc2 = pr.t_cmb * pr.t_cmb;
+  L.Eir = pr.ir_mode == 1 ? c.eir[i] : ARAD * tc2 * tc2 / pr.c_red;
+  bool ok = finite_bits(nh) && nh > 0.0 && finite_bits(ne) && ne >= 0.0 && finite_bits(nf) &&
+            nf >= 0.0 && finite_bits(z) && z >= 0.0 && finite_bits(L.y2) && L.y2 >= 0.0 &&
+            finite_bits(L.ye) && L.ye >= 0.0 && finite_bits(L.E) && L.E > 0.0 &&
+            finite_bits(L.Td) && L.Td > 0.0;
+  if (pr.ir_mode == 1) ok = ok && finite_bits(L.Eir) && L.Eir > 0.0;
+  if (!ok) {
+    const double nan = __longlong_as_double(0x7ff8000000000000ll);
+    if (c.y_h) c.y_h[i] = nan;
+    if (c.y_hp) c.y_hp[i] = nan;
+    if (c.y_hm) c.y_hm[i] = nan;
+    if (c.tgas) c.tgas[i] = nan;
+    if (c.nsub) c.nsub[i] = 0;
+    if (c.niter) c.niter[i] = 0;
+    if (c.flags) c.flags[i] = F_INVALID;
+    return false;
+  }
+  cell_consts(nt, pr, nh, ne, nf, z, L.ck);
+  L.Tiso = L.E / (KB * nh * cvk(pr, L.y2, L.ye));
+  L.rem = dt;
+  L.nsub = 0;
+  L.nit = 0;
+  L.fl = 0;
+  renormalise<R>(nt, pr, L, pr.thermal_mode == 1);
+  return true;
+}
+
+template <class R>
+__device__ void store_cell(const Net& nt, const Par& pr, const Cells& c, int64_t i,
+                           const Lane& L) {
+  c.y_h2[i] = L.y2;
+  c.y_e[i] = L.ye;
+  c.eint[i] = L.E;
+  c.tdust[i] = L.Td;
+  if (pr.ir_mode == 1) c.eir[i] = L.Eir;
+  const bool iso = pr.thermal_mode == 1;
+  const double T = iso ? L.Tiso : L.E / (KB * L.ck.n * cvk(pr, L.y2, L.ye));
+  if (c.y_h || c.y_hp || c.y_hm) {
+    const double r = hm_ratio<R>(nt, T);
+    const double yhm = r * L.ye;
+    const double yhp = L.ye + yhm;
+    if (c.y_h) c.y_h[i] = 1.0 - 2.0 * L.y2 - yhp - yhm;
+    if (c.y_hp) c.y_hp[i] = yhp;
+    if (c.y_hm) c.y_hm[i] = yhm;
+  }
+  if (c.tgas) c.tgas[i] = T;
+  if (c.nsub) c.nsub[i] = L.nsub;
+  if (c.niter) c.niter[i] = L.nit;
+  if (c.flags) c.flags[i] = L.fl;
+}
+
+__device__ inline unsigned lanes_below(unsigned long long mask) {
+  return __builtin_amdgcn_mbcnt_hi(unsigned(mask >> 32), __builtin_amdgcn_mbcnt_lo(unsigned(mask), 0u));
+}
+
+// The network and parameters are re-read from the context's device copy
+// (constant address space, scalar loads) at every subcycle.  Holding the
+// ~100 uniform binary64 values they feed across the whole cell loop costs
+// SGPR spills and VGPR copies; the opaque pointer keeps the loads (and the
+// arithmetic on them) inside the loop.
+typedef const __attribute__((address_space(4))) Net CNet;
+typedef const __attribute__((address_space(4))) Par CPar;
+__device__ inline const Net& fresh(const Net* p) {
+  CNet* q = (CNet*)p;
+  asm volatile("" : "+s"(q));
+  return *(const Net*)q;
+}
+__device__ inline const Par& fresh(const Par* p) {
+  CPar* q = (CPar*)p;
+  asm volatile("" : "+s"(q));
+  return *(const Par*)q;
+}
+
+// The kernel's own argument block, re-read (scalar loads) wherever it is
+// used inside the cell loop instead of being held in SGPRs across it: the
+// ~40 pointers and scalars it holds would otherwise spill to VGPR lanes.
+template <class A>
+__device__ inline const A& kargs() {
+  typedef const __attribute__((address_space(4))) A CA;
+  CA* p = (CA*)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(p));
+  return *(const A*)p;
+}
+
+}  // namespace
+}  // namespace sfk

@@ -6,15 +6,18 @@
 //   admit    -> arena range reserved against the HBM budget, cells copied
 //               from the caller's buffers into the arena (copy stream)
 //   publish  -> ring entry written into coherent pinned host memory, then
-//               the published count is raised (release)
+//               the published count is raised (release); each precision has
+//               one ring per claim class: one class for all requests
+//               (admission order, the default) or one per AMR level, the
+//               drain then serving the highest level with work first
 //   drain    -> the persistent drain kernel, replayed from a HIP graph on
 //               the drain stream whenever it is not running and published
 //               work is left, claims cells lane by lane; the lane storing a
 //               request's last cell raises that request's done word
 //   copy-out -> results copied back into the caller's buffers (copy stream);
 //               the arena range is released and the request is complete.
-// One scheduler thread owns every stage after submit.  The drain kernel is
-// launched on fewer CUs than the device has, so the copy kernels of newly
+// One scheduler thread owns every stage after submit.  The drain streams are
+// masked to fewer CUs than the device has, so the copy kernels of newly
 // admitted and finished requests always find a free CU.
 #include "sfserve.h"
 
@@ -43,7 +46,8 @@ struct Req {
   uint64_t ticket = 0;
   sfc_request r{};
   int prec = 0;
-  uint64_t seq = 0;      // sequence number in its precision's ring
+  int cls = 0;           // claim class (AMR level clamped to the class range)
+  uint64_t seq = 0;      // sequence number in its class's ring
   int64_t off = -1;      // first arena cell
   double t_submit = 0, t_admit = 0, t_done = 0;
   hipEvent_t ev = nullptr;
@@ -90,22 +94,28 @@ class Ranges {
   std::map<int64_t, int64_t> free_;
 };
 
-// One ring (and drain graph) per precision.
+constexpr int kSlots = sfk::kClasses * sfk::kRing;
+
+size_t slot_of(const Req* r) { return size_t(r->cls) * sfk::kRing + size_t(r->seq % sfk::kRing); }
+
+// One set of rings (and one drain graph) per precision; every array below
+// is class-major, kRing slots per class.
 struct Queue {
-  sfk::RingEntry* ring = nullptr;      // coherent pinned host memory
-  uint64_t* published = nullptr;       // coherent pinned host memory
-  uint64_t* done = nullptr;            // coherent pinned host memory, kRing words
+  sfk::RingEntry* ring = nullptr;      // coherent pinned host memory, kSlots entries
+  uint64_t* published = nullptr;       // coherent pinned host memory, kClasses words
+  uint64_t* done = nullptr;            // coherent pinned host memory, kSlots words
   sfk::RingEntry* d_ring = nullptr;    // device views of the three above
   uint64_t* d_published = nullptr;
   uint64_t* d_done = nullptr;
-  unsigned long long* head = nullptr;  // device: oldest request with unclaimed cells
-  uint32_t* claimed = nullptr;         // device, kRing: cells handed out per slot
-  int32_t* remaining = nullptr;        // device, kRing: cells not yet stored per slot
-  uint64_t next_seq = 0;
-  std::deque<Req*> inflight;           // admitted, done not yet seen; seq order
+  unsigned long long* ctr = nullptr;   // device, 3 x kClasses + 1: head | seen | staged | newest
+  uint32_t* claimed = nullptr;         // device, kSlots: cells handed out per slot
+  int32_t* remaining = nullptr;        // device, kSlots: cells not yet stored per slot
+  uint64_t next_seq[sfk::kClasses] = {};
+  std::deque<Req*> inflight[sfk::kClasses];  // admitted, done not yet seen; seq order
+  uint64_t pub_total = 0;              // requests published, all classes
   int64_t running = 0;                 // published, done not yet seen
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec[2] = {nullptr, nullptr};  // one per drain slot (launches of one exec serialise)
+  hipGraph_t graph[2] = {nullptr, nullptr};     // one per drain slot (its slot is an argument)
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
   int grid = 0;
 };
 
@@ -123,12 +133,18 @@ struct Server {
   // drain kernel's waves leave once idle, but the kernel lives on while a
   // few of them finish long cells; a second kernel launched meanwhile takes
   // the freed slots, so newly published requests find a full complement of
-  // waves instead of the few survivors.
+  // waves instead of the few survivors.  Once the newer kernel's waves
+  // start, the older kernel's waves stop claiming and leave as their cells
+  // finish, so its slot frees up for the next launch.
   hipStream_t drain_stream[2] = {nullptr, nullptr};
   hipEvent_t drain_ev[2] = {nullptr, nullptr};
   bool drain_live[2] = {false, false};
   int drain_prec[2] = {0, 0};
   uint64_t drain_pub[2] = {0, 0};  // requests of its precision published at its launch
+  uint64_t* gen = nullptr;         // coherent pinned host memory, per slot: latest launch generation
+  uint64_t* d_gen = nullptr;
+  uint64_t gen_count = 0;
+  bool fifo = true;                // every request in class 0 (admission order only)
   int last_prec = 1;
   Ranges ranges;
 
@@ -192,8 +208,10 @@ sfk::CopyArgs copy_args(Server* s, const Req* r) {
   a.arena = s->arena;
   a.off = r->off;
   a.z_default = s->cfg.par.z_default;
-  a.remaining_slot = s->q[r->prec].remaining + (r->seq % sfk::kRing);
-  a.claimed_slot = s->q[r->prec].claimed + (r->seq % sfk::kRing);
+  Queue& q = s->q[r->prec];
+  a.remaining_slot = q.remaining + slot_of(r);
+  a.claimed_slot = q.claimed + slot_of(r);
+  a.staged = q.ctr + 2 * sfk::kClasses + r->cls;
   a.ir_evolve = s->evolve ? 1 : 0;
   return a;
 }
@@ -239,9 +257,10 @@ bool step_once(Server* s) {
   // 2. done words raised by the drain kernel -> copy results back
   for (int p = 0; p < 2; ++p) {
     Queue& q = s->q[p];
-    for (Req* r : q.inflight) {
+    for (auto& fl : q.inflight) {
+    for (Req* r : fl) {
       if (r->st != St::Running || r->done_seen) continue;
-      const uint64_t d = __atomic_load_n(q.done + (r->seq % sfk::kRing), __ATOMIC_ACQUIRE);
+      const uint64_t d = __atomic_load_n(q.done + slot_of(r), __ATOMIC_ACQUIRE);
       if (d != r->seq + 1) continue;
       r->done_seen = true;
       q.running -= 1;
@@ -254,7 +273,8 @@ bool step_once(Server* s) {
       s->copyout.push_back(r);
       moved = true;
     }
-    while (!q.inflight.empty() && q.inflight.front()->done_seen) q.inflight.pop_front();
+    while (!fl.empty() && fl.front()->done_seen) fl.pop_front();
+    }
   }
   // 3. finished copy-ins -> publish, in admission order
   while (!s->staging.empty()) {
@@ -266,14 +286,16 @@ bool step_once(Server* s) {
     put_event(s, r->ev);
     r->ev = nullptr;
     Queue& q = s->q[r->prec];
-    sfk::RingEntry& re = q.ring[r->seq % sfk::kRing];
+    sfk::RingEntry& re = q.ring[slot_of(r)];
     re.arena_off = uint64_t(r->off);
     re.n = uint64_t(r->r.cells.n);
     re.dt = r->r.dt_seconds;
+    re.level = uint64_t(r->r.level < 0 ? 0 : r->r.level > 255 ? 255 : r->r.level);
     __atomic_store_n(&re.seq, r->seq, __ATOMIC_RELEASE);
-    __atomic_store_n(q.published, r->seq + 1, __ATOMIC_RELEASE);
+    __atomic_store_n(q.published + r->cls, r->seq + 1, __ATOMIC_RELEASE);
     r->st = St::Running;
     q.running += 1;
+    q.pub_total += 1;
     moved = true;
   }
   // 4. admission: arrival order, while the arena and the ring have room
@@ -287,12 +309,13 @@ bool step_once(Server* s) {
   while (!s->pending.empty()) {
     Req* r = s->pending.front();
     Queue& q = s->q[r->prec];
-    if (!q.inflight.empty() && q.next_seq - q.inflight.front()->seq >= uint64_t(sfk::kRing)) break;
+    auto& fl = q.inflight[r->cls];
+    if (!fl.empty() && q.next_seq[r->cls] - fl.front()->seq >= uint64_t(sfk::kRing)) break;
     const int64_t off = s->ranges.alloc(r->r.cells.n);
     if (off < 0) break;
     s->pending.pop_front();
     r->off = off;
-    r->seq = q.next_seq++;
+    r->seq = q.next_seq[r->cls]++;
     r->ev = get_event(s);
     if (!r->ev) return set_fatal(s, "event pool"), false;
     const sfk::CopyArgs a = copy_args(s, r);
@@ -300,7 +323,7 @@ bool step_once(Server* s) {
     if (!hip_ok(s, hipEventRecord(r->ev, s->copy_stream), "event record")) return false;
     r->t_admit = now();
     r->st = St::Staging;
-    q.inflight.push_back(r);
+    fl.push_back(r);
     s->staging.push_back(r);
     moved = true;
   }
@@ -325,16 +348,18 @@ bool step_once(Server* s) {
     }
     if (pick < 0 && s->drain_live[o]) {
       const int p = s->drain_prec[o];
-      const uint64_t pub = __atomic_load_n(s->q[p].published, __ATOMIC_RELAXED);
-      if (s->q[p].running > 0 && pub > s->drain_pub[o]) pick = p;
+      if (s->q[p].running > 0 && s->q[p].pub_total > s->drain_pub[o]) pick = p;
     }
     if (pick < 0) continue;
     Queue& q = s->q[pick];
+    // a launch's waves read its generation when they start; older waves of
+    // the same precision stop claiming once a newer launch has started
+    __atomic_store_n(s->gen + i, ++s->gen_count, __ATOMIC_RELEASE);
     if (!hip_ok(s, hipGraphLaunch(q.exec[i], s->drain_stream[i]), "graph launch")) return false;
     if (!hip_ok(s, hipEventRecord(s->drain_ev[i], s->drain_stream[i]), "event record")) return false;
     s->drain_live[i] = true;
     s->drain_prec[i] = pick;
-    s->drain_pub[i] = __atomic_load_n(q.published, __ATOMIC_RELAXED);
+    s->drain_pub[i] = q.pub_total;
     s->last_prec = pick;
     moved = true;
   }
@@ -381,14 +406,16 @@ void free_all(Server* s) {
   for (auto& q : s->q) {
     for (auto& x : q.exec)
       if (x) (void)hipGraphExecDestroy(x);
-    if (q.graph) (void)hipGraphDestroy(q.graph);
+    for (auto& g : q.graph)
+      if (g) (void)hipGraphDestroy(g);
     if (q.ring) (void)hipHostFree(q.ring);
     if (q.published) (void)hipHostFree(q.published);
     if (q.done) (void)hipHostFree(q.done);
-    if (q.head) (void)hipFree(q.head);
+    if (q.ctr) (void)hipFree(q.ctr);
     if (q.claimed) (void)hipFree(q.claimed);
     if (q.remaining) (void)hipFree(q.remaining);
   }
+  if (s->gen) (void)hipHostFree(s->gen);
   for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
   for (auto& e : s->drain_ev)
     if (e) (void)hipEventDestroy(e);
@@ -463,7 +490,7 @@ Server* create(const Config& cfg, std::string* err, int* code) {
   A.flags = reinterpret_cast<uint32_t*>(inext());
   s->ranges.reset(s->cap);
 
-  // The copy stream carries a CU mask (all CUs): a masked stream gets a
+  // Every stream carries a CU mask (all CUs): a masked stream gets a
   // hardware queue of its own.  Plain streams share the few hardware queues
   // round-robin, and a copy kernel that lands on the drain's queue waits
   // until the persistent drain kernel ends, so admission (copy-in) and
@@ -477,6 +504,14 @@ Server* create(const Config& cfg, std::string* err, int* code) {
       hipEventCreateWithFlags(&s->drain_ev[0], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&s->drain_ev[1], hipEventDisableTiming) != hipSuccess)
     return fail(s, SFC_E_DEVICE, "stream/event creation");
+  {
+    const unsigned fl = hipHostMallocCoherent | hipHostMallocMapped;
+    if (hipHostMalloc(reinterpret_cast<void**>(&s->gen), 256, fl) != hipSuccess)
+      return fail(s, SFC_E_NOMEM, "pinned host allocation");
+    std::memset(s->gen, 0, 256);
+    if (hipHostGetDevicePointer(reinterpret_cast<void**>(&s->d_gen), s->gen, 0) != hipSuccess)
+      return fail(s, SFC_E_DEVICE, "host pointer mapping");
+  }
 
   int khz = 0;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, cfg.device) != hipSuccess ||
@@ -485,31 +520,33 @@ Server* create(const Config& cfg, std::string* err, int* code) {
   const double tps = double(khz) * 1e3;
   const int reserve = int(env_num("SFC_SERVE_RESERVE_CUS", 8));
   const int cus = cfg.cus - (reserve >= 0 && reserve < cfg.cus ? reserve : 0);
+  s->fifo = env_num("SFC_SERVE_LEVEL_CLAIMS", 0.0) == 0.0;
 
   for (int prec = 0; prec < 2; ++prec) {
     Queue& q = s->q[prec];
     const unsigned fl = hipHostMallocCoherent | hipHostMallocMapped;
-    if (hipHostMalloc(reinterpret_cast<void**>(&q.ring), sizeof(sfk::RingEntry) * sfk::kRing, fl) !=
+    if (hipHostMalloc(reinterpret_cast<void**>(&q.ring), sizeof(sfk::RingEntry) * kSlots, fl) !=
             hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&q.published), 256, fl) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&q.done), sizeof(uint64_t) * sfk::kRing, fl) !=
+        hipHostMalloc(reinterpret_cast<void**>(&q.done), sizeof(uint64_t) * kSlots, fl) !=
             hipSuccess)
       return fail(s, SFC_E_NOMEM, "pinned host allocation");
-    std::memset(q.ring, 0xff, sizeof(sfk::RingEntry) * sfk::kRing);
-    *q.published = 0;
-    std::memset(q.done, 0, sizeof(uint64_t) * sfk::kRing);
+    std::memset(q.ring, 0xff, sizeof(sfk::RingEntry) * kSlots);
+    std::memset(q.published, 0, sizeof(uint64_t) * sfk::kClasses);
+    std::memset(q.done, 0, sizeof(uint64_t) * kSlots);
     if (hipHostGetDevicePointer(reinterpret_cast<void**>(&q.d_ring), q.ring, 0) != hipSuccess ||
         hipHostGetDevicePointer(reinterpret_cast<void**>(&q.d_published), q.published, 0) !=
             hipSuccess ||
         hipHostGetDevicePointer(reinterpret_cast<void**>(&q.d_done), q.done, 0) != hipSuccess)
       return fail(s, SFC_E_DEVICE, "host pointer mapping");
-    if (hipMalloc(&q.head, sizeof(unsigned long long)) != hipSuccess ||
-        hipMalloc(&q.claimed, sizeof(uint32_t) * sfk::kRing) != hipSuccess ||
-        hipMalloc(&q.remaining, sizeof(int32_t) * sfk::kRing) != hipSuccess)
+    const size_t nctr = 3 * sfk::kClasses + 1;
+    if (hipMalloc(&q.ctr, sizeof(unsigned long long) * nctr) != hipSuccess ||
+        hipMalloc(&q.claimed, sizeof(uint32_t) * kSlots) != hipSuccess ||
+        hipMalloc(&q.remaining, sizeof(int32_t) * kSlots) != hipSuccess)
       return fail(s, SFC_E_NOMEM, "served counters");
-    if (hipMemset(q.head, 0, sizeof(unsigned long long)) != hipSuccess ||
-        hipMemset(q.claimed, 0, sizeof(uint32_t) * sfk::kRing) != hipSuccess ||
-        hipMemset(q.remaining, 0, sizeof(int32_t) * sfk::kRing) != hipSuccess)
+    if (hipMemset(q.ctr, 0, sizeof(unsigned long long) * nctr) != hipSuccess ||
+        hipMemset(q.claimed, 0, sizeof(uint32_t) * kSlots) != hipSuccess ||
+        hipMemset(q.remaining, 0, sizeof(int32_t) * kSlots) != hipSuccess)
       return fail(s, SFC_E_DEVICE, "served counters");
 
     sfk::ServedArgs a{};
@@ -518,7 +555,11 @@ Server* create(const Config& cfg, std::string* err, int* code) {
     a.arena = s->arena;
     a.ring = q.d_ring;
     a.published = q.d_published;
-    a.head = q.head;
+    a.head = q.ctr;
+    a.seen = q.ctr + sfk::kClasses;
+    a.staged = q.ctr + 2 * sfk::kClasses;
+    a.newest = q.ctr + 3 * sfk::kClasses;
+    a.gen = s->d_gen;
     a.claimed = q.claimed;
     a.remaining = q.remaining;
     a.done = q.d_done;
@@ -527,18 +568,21 @@ Server* create(const Config& cfg, std::string* err, int* code) {
     a.backoff_ticks = uint64_t(10e-6 * tps);
     a.backoff_max_ticks = uint64_t(500e-6 * tps);
     a.refill_min = cfg.refill_min;
+    a.level_prio = env_num("SFC_SERVE_LEVEL_PRIO", 1.0) != 0.0 ? 1 : 0;
     a.netc = cfg.netc;
     a.parc = cfg.parc;
     q.grid = cus * sfk::served_blocks_per_cu(prec);
-    if (hipStreamBeginCapture(s->drain_stream[0], hipStreamCaptureModeThreadLocal) != hipSuccess)
-      return fail(s, SFC_E_DEVICE, "graph capture");
-    const hipError_t le = sfk::launch_served(a, prec, q.grid, s->drain_stream[0]);
-    const hipError_t ce = hipStreamEndCapture(s->drain_stream[0], &q.graph);
-    if (le != hipSuccess || ce != hipSuccess)
-      return fail(s, SFC_E_DEVICE, "graph capture of the drain kernel");
-    if (hipGraphInstantiate(&q.exec[0], q.graph, nullptr, nullptr, 0) != hipSuccess ||
-        hipGraphInstantiate(&q.exec[1], q.graph, nullptr, nullptr, 0) != hipSuccess)
-      return fail(s, SFC_E_DEVICE, "graph instantiation");
+    for (int i = 0; i < 2; ++i) {
+      a.slot = i;
+      if (hipStreamBeginCapture(s->drain_stream[0], hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(s, SFC_E_DEVICE, "graph capture");
+      const hipError_t le = sfk::launch_served(a, prec, q.grid, s->drain_stream[0]);
+      const hipError_t ce = hipStreamEndCapture(s->drain_stream[0], &q.graph[i]);
+      if (le != hipSuccess || ce != hipSuccess)
+        return fail(s, SFC_E_DEVICE, "graph capture of the drain kernel");
+      if (hipGraphInstantiate(&q.exec[i], q.graph[i], nullptr, nullptr, 0) != hipSuccess)
+        return fail(s, SFC_E_DEVICE, "graph instantiation");
+    }
   }
   if (hipDeviceSynchronize() != hipSuccess) return fail(s, SFC_E_DEVICE, "device sync");
   s->th = std::thread(run, s);
@@ -557,6 +601,7 @@ int submit(Server* s, const sfc_request& req, uint64_t* ticket, std::string* err
   if (!r) return SFC_E_NOMEM;
   r->r = req;
   r->prec = req.precision;
+  r->cls = s->fifo ? 0 : (req.level < 0 ? 0 : req.level >= sfk::kClasses ? sfk::kClasses - 1 : req.level);
   r->t_submit = now();
   std::lock_guard<std::mutex> lk(s->mu);
   if (!s->fatal.empty()) {

@@ -7,7 +7,7 @@
 #include <string>
 
 #include "sfchem.h"
-#include "sfk.h"
+#include "sfk_served.h"
 
 namespace sfserve {
 

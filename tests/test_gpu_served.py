@@ -179,3 +179,48 @@ def test_served_errors_and_tickets():
             ctx.poll(t)  # a ticket is released once reported
     finally:
         ctx.close()
+
+
+def _latency_pair(level_claims):
+    """A large level-0 request, then a small level-5 request of cheap cells
+    right behind it; returns (fine, coarse) latency in seconds."""
+    import os
+    import torch
+    sfc = _sfc()
+    coarse = W.uniform_population(393216, seed_offset=11)
+    pool = W.uniform_population(20000, seed_offset=12)
+    keep = np.flatnonzero(pool["nh"] < 1e3)[:512]
+    fine = {k: v[keep] for k, v in pool.items()}
+    old = os.environ.get("SFC_SERVE_LEVEL_CLAIMS")
+    os.environ["SFC_SERVE_LEVEL_CLAIMS"] = "1" if level_claims else "0"
+    try:
+        ctx = sfc.Context(served_budget_bytes=256 * MIB)
+    finally:
+        if old is None:
+            del os.environ["SFC_SERVE_LEVEL_CLAIMS"]
+        else:
+            os.environ["SFC_SERVE_LEVEL_CLAIMS"] = old
+    try:
+        bc, bf = sfc.to_device(coarse), sfc.to_device(fine)
+        torch.cuda.synchronize()
+        print(f"[served] latency pair, level claims {level_claims}", flush=True)
+        tc = ctx.submit(bc, 3.15576e11, sfc.FP64, level=0, tag=0)
+        tf = ctx.submit(bf, 3.15576e11 / 32, sfc.FP64, level=5, tag=1)
+        ctx.drain()
+        rc, rf = ctx.poll(tc), ctx.poll(tf)
+    finally:
+        ctx.close()
+    assert rc["status"] == 0 and rf["status"] == 0
+    return rf["t_done"] - rf["t_submit"], rc["t_done"] - rc["t_submit"]
+
+
+def test_served_level_claims_take_finer_level_first():
+    """With SFC_SERVE_LEVEL_CLAIMS=1 idle lanes take the finer level's cells
+    before the rest of an older, coarser request; in admission order (the
+    default) the fine request waits until every coarse cell is handed out."""
+    f_lvl, c_lvl = _latency_pair(True)
+    f_adm, c_adm = _latency_pair(False)
+    print(f"[served] fine/coarse latency: level claims {f_lvl * 1e3:.1f}/{c_lvl * 1e3:.1f} ms, "
+          f"admission order {f_adm * 1e3:.1f}/{c_adm * 1e3:.1f} ms", flush=True)
+    assert f_lvl < c_lvl
+    assert f_lvl < 0.5 * f_adm
