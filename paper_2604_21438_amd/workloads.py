@@ -269,7 +269,7 @@ def _gaussian_field(g, side: int, slope: float = 11.0 / 3.0):
     amp = np.zeros_like(kk)
     amp[kk > 0] = kk[kk > 0] ** (-slope / 2.0)
     spec = amp * (g.normal(size=kk.shape) + 1j * g.normal(size=kk.shape))
-    f = np.fft.irfftn(spec, s=(side, side, side))
+    f = np.fft.irfftn(spec, s=(side, side, side), axes=(0, 1, 2))
     return (f - f.mean()) / f.std()
 
 

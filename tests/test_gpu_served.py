@@ -224,3 +224,54 @@ def test_served_level_claims_take_finer_level_first():
           f"admission order {f_adm * 1e3:.1f}/{c_adm * 1e3:.1f} ms", flush=True)
     assert f_lvl < c_lvl
     assert f_lvl < 0.5 * f_adm
+
+
+def test_served_amr_chain_matches_plain():
+    """A small GMC-like hierarchy (4 levels of 8^3 blocks, level L advanced
+    2^L times with dt = 10 kyr / 2^L): each level submits its next substep
+    as soon as the previous one is done, so requests of all levels overlap
+    and the drain relaunches, hands over and prioritises by level on the
+    way.  Each level's state after the coarse step is bitwise the state of
+    the plain step called level by level."""
+    import time
+    import torch
+    sfc = _sfc()
+    levels = W.gmc_levels(target_cells=40000, base_side=16)
+    nl = len(levels)
+    assert nl >= 3
+    for prec in (sfc.FP64, sfc.MIXED):
+        plain = sfc.Context(dust_factor=1.0, z_default=0.1)
+        served = sfc.Context(dust_factor=1.0, z_default=0.1, served_budget_bytes=64 * MIB)
+        try:
+            ref = [sfc.to_device(lv["cells"]) for lv in levels]
+            for L in range(nl):
+                for _ in range(2 ** L):
+                    plain.step(ref[L], levels[L]["dt"], prec)
+            torch.cuda.synchronize()
+            bufs = [sfc.to_device(lv["cells"]) for lv in levels]
+            torch.cuda.synchronize()
+            print(f"[served] amr chain, precision {prec}, cells per level "
+                  f"{[lv['cells']['nh'].shape[0] for lv in levels]}", flush=True)
+            remaining = [2 ** L for L in range(nl)]
+            inflight = [None] * nl
+            deadline = time.monotonic() + 120.0
+            while any(remaining) or any(t is not None for t in inflight):
+                assert time.monotonic() < deadline
+                for L in range(nl):
+                    if inflight[L] is not None:
+                        r = served.poll(inflight[L])
+                        if r is not None:
+                            assert r["status"] == 0 and r["level"] == L
+                            inflight[L] = None
+                    if inflight[L] is None and remaining[L] > 0:
+                        inflight[L] = served.submit(bufs[L], levels[L]["dt"], prec, level=L)
+                        remaining[L] -= 1
+                time.sleep(200e-6)
+            torch.cuda.synchronize()
+            for L in range(nl):
+                a = {k: v.cpu().numpy() for k, v in bufs[L].items()}
+                b = {k: v.cpu().numpy() for k, v in ref[L].items()}
+                _same(a, b, f"level {L} precision {prec}")
+        finally:
+            served.close()
+            plain.close()
