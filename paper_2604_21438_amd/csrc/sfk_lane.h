@@ -85,7 +85,7 @@ __device__ inline double fsqrt(double x) {
 // neither 0 nor infinite); then e^x = 2^(n >> 5) 2^((n & 31)/32) e^r with
 // |r| <= ln2/64, e^r - 1 from its Taylor series to r^6/720 (truncation
 // below 4e-18 relative), and 2^(j/32) (correctly rounded) from a 32-entry
-// table staged in LDS by each kernel (stage_exp_table).  Within one ulp of
+// table staged in LDS by each kernel (stage_tables).  Within one ulp of
 // e^x; 0 below the binary64 range, infinity above it.  About 16 VALU
 // instructions and one LDS read against ~21 for the library routine, whose
 // wider reduction interval needs a degree-11 polynomial.
@@ -100,10 +100,153 @@ __constant__ double kExp2j32[32] = {
     0x1.d5818dcfba487p+0, 0x1.dfc97337b9b5fp+0, 0x1.ea4afa2a490dap+0, 0x1.f50765b6e4540p+0};
 __shared__ double lds_exp2j32[32];
 
+// ln x in binary64 for positive normal x.  x = m 2^e with m in [0.5, 1);
+// c_j = 1/2 + j/256 is the node nearest m (j = 0..128), and with
+// i_j = RN(1/c_j), ln x = e ln2 - ln i_j + ln(1 + r), r = m i_j - 1 exact
+// to one rounding and |r| <= 1/256, ln(1 + r) by its series to r^7
+// (truncation below 2e-18 relative).  -ln i_j is tabulated in high
+// precision as a part on the 2^-32 grid plus a remainder, like ln 2, so
+// e ln2 + (-ln i_j) is exact in binary64: ln 1 = 0 exactly and results near
+// 1 keep their relative accuracy.  Within one ulp; ~21 VALU instructions
+// and two LDS reads against ~50 for the library's double-double routine.
+__constant__ double kLogTab[129][4] = {
+    {0x1.0000000000000p+1, -0x1.62e42ff000000p-1, 0x1.718432a1b0e26p-35, 0.0},
+    {0x1.fc07f01fc07f0p+0, -0x1.5ee82aa200000p-1, -0x1.064800e033692p-35, 0.0},
+    {0x1.f81f81f81f820p+0, -0x1.5af405c400000p-1, 0x1.36c3fb38a7de7p-34, 0.0},
+    {0x1.f44659e4a4271p+0, -0x1.5707a26c00000p-1, 0x1.1ce67e7400cd0p-35, 0.0},
+    {0x1.f07c1f07c1f08p+0, -0x1.5322e26800000p-1, -0x1.9e15dcc45d257p-35, 0.0},
+    {0x1.ecc07b301ecc0p+0, -0x1.4f45a83600000p-1, 0x1.6c79d145b64eep-35, 0.0},
+    {0x1.e9131abf0b767p+0, -0x1.4b6fd6fa00000p-1, 0x1.1e7c175d42567p-34, 0.0},
+    {0x1.e573ac901e574p+0, -0x1.47a1527e00000p-1, -0x1.145a742a0d654p-34, 0.0},
+    {0x1.e1e1e1e1e1e1ep+0, -0x1.43d9ff3000000p-1, 0x1.b70ed427a4083p-35, 0.0},
+    {0x1.de5d6e3f8868ap+0, -0x1.4019c21200000p-1, -0x1.72a4b31b3c3cep-35, 0.0},
+    {0x1.dae6076b981dbp+0, -0x1.3c6080c400000p-1, 0x1.2809581b3e7f1p-34, 0.0},
+    {0x1.d77b654b82c34p+0, -0x1.38ae217200000p-1, 0x1.a2460feaed55ap-35, 0.0},
+    {0x1.d41d41d41d41dp+0, -0x1.35028ada00000p-1, 0x1.39bd4301ab606p-36, 0.0},
+    {0x1.d0cb58f6ec074p+0, -0x1.315da44400000p-1, 0x1.7f2ea4278b41ep-34, 0.0},
+    {0x1.cd85689039b0bp+0, -0x1.2dbf557c00000p-1, 0x1.e417a06507b9ep-34, 0.0},
+    {0x1.ca4b3055ee191p+0, -0x1.2a2786d000000p-1, -0x1.d820da17cf2f1p-34, 0.0},
+    {0x1.c71c71c71c71cp+0, -0x1.2696211400000p-1, 0x1.648dc0f882913p-34, 0.0},
+    {0x1.c3f8f01c3f8f0p+0, -0x1.230b0d8c00000p-1, 0x1.43683fcc8dbcdp-37, 0.0},
+    {0x1.c0e070381c0e0p+0, -0x1.1f8635fc00000p-1, -0x1.859616f4d8060p-35, 0.0},
+    {0x1.bdd2b899406f7p+0, -0x1.1c07849a00000p-1, -0x1.cc00daa6f76b8p-34, 0.0},
+    {0x1.bacf914c1bad0p+0, -0x1.188ee41000000p-1, 0x1.b86b23b10754cp-34, 0.0},
+    {0x1.b7d6c3dda338bp+0, -0x1.151c3f7000000p-1, 0x1.ad3dc16f45276p-34, 0.0},
+    {0x1.b4e81b4e81b4fp+0, -0x1.11af823c00000p-1, -0x1.d6aa0be111889p-35, 0.0},
+    {0x1.b2036406c80d9p+0, -0x1.0e48986200000p-1, 0x1.c663d6a7f87ffp-34, 0.0},
+    {0x1.af286bca1af28p+0, -0x1.0ae76e2e00000p-1, 0x1.f560c79477818p-34, 0.0},
+    {0x1.ac5701ac5701bp+0, -0x1.078bf05400000p-1, 0x1.8752f4fb7c241p-34, 0.0},
+    {0x1.a98ef606a63bep+0, -0x1.04360be800000p-1, 0x1.3f8a4f2ff3caap-34, 0.0},
+    {0x1.a6d01a6d01a6dp+0, -0x1.00e5ae5c00000p-1, 0x1.bf0a9e11d8b94p-34, 0.0},
+    {0x1.a41a41a41a41ap+0, -0x1.fb358af800000p-2, 0x1.6ddf1c0b87d37p-36, 0.0},
+    {0x1.a16d3f97a4b02p+0, -0x1.f4aa7ee000000p-2, -0x1.8c96e32b780a5p-37, 0.0},
+    {0x1.9ec8e951033d9p+0, -0x1.ee2a156c00000p-2, 0x1.7d83692e96e3fp-35, 0.0},
+    {0x1.9c2d14ee4a102p+0, -0x1.e7b42c3c00000p-2, -0x1.dad744df591a8p-34, 0.0},
+    {0x1.999999999999ap+0, -0x1.e148a1a400000p-2, 0x1.8d9316b207323p-34, 0.0},
+    {0x1.970e4f80cb872p+0, -0x1.dae7548400000p-2, -0x1.92c290a53e474p-35, 0.0},
+    {0x1.948b0fcd6e9e0p+0, -0x1.d490246c00000p-2, -0x1.efa6a75fd34edp-34, 0.0},
+    {0x1.920fb49d0e229p+0, -0x1.ce42f18000000p-2, -0x1.91d0eb798270bp-36, 0.0},
+    {0x1.8f9c18f9c18fap+0, -0x1.c7ff9c7400000p-2, -0x1.55327111f56dbp-36, 0.0},
+    {0x1.8d3018d3018d3p+0, -0x1.c1c6069400000p-2, 0x1.7189cfc00b8f4p-40, 0.0},
+    {0x1.8acb90f6bf3aap+0, -0x1.bb9611b800000p-2, -0x1.c5f7f6fd0299ap-39, 0.0},
+    {0x1.886e5f0abb04ap+0, -0x1.b56fa04400000p-2, -0x1.8a429a94b6106p-36, 0.0},
+    {0x1.8618618618618p+0, -0x1.af52952400000p-2, -0x1.19b9eceab622fp-35, 0.0},
+    {0x1.83c977ab2beddp+0, -0x1.a93ed3c800000p-2, -0x1.5b3c60657d4efp-35, 0.0},
+    {0x1.8181818181818p+0, -0x1.a334402400000p-2, 0x1.b058777500c51p-34, 0.0},
+    {0x1.7f405fd017f40p+0, -0x1.9d32bea000000p-2, -0x1.5ed3a0c3de5e8p-34, 0.0},
+    {0x1.7d05f417d05f4p+0, -0x1.973a343000000p-2, -0x1.356ad8ec5afd2p-34, 0.0},
+    {0x1.7ad2208e0ecc3p+0, -0x1.914a863400000p-2, -0x1.bf688b0ad119dp-34, 0.0},
+    {0x1.78a4c8178a4c8p+0, -0x1.8b639a8800000p-2, -0x1.65be8c786863fp-35, 0.0},
+    {0x1.767dce434a9b1p+0, -0x1.8585577800000p-2, 0x1.2340556199991p-34, 0.0},
+    {0x1.745d1745d1746p+0, -0x1.7fafa3bc00000p-2, -0x1.8151c6de6fdb5p-34, 0.0},
+    {0x1.724287f46debcp+0, -0x1.79e2668800000p-2, 0x1.8261402d102e9p-37, 0.0},
+    {0x1.702e05c0b8170p+0, -0x1.741d876c00000p-2, -0x1.9eec384a4ee30p-36, 0.0},
+    {0x1.6e1f76b4337c7p+0, -0x1.6e60ee6c00000p-2, 0x1.0e68d55a83dddp-34, 0.0},
+    {0x1.6c16c16c16c17p+0, -0x1.68ac83e800000p-2, -0x1.c6a14ca64eaddp-34, 0.0},
+    {0x1.6a13cd1537290p+0, -0x1.630030b400000p-2, 0x1.54ede11f398d7p-36, 0.0},
+    {0x1.6816816816817p+0, -0x1.5d5bddf400000p-2, -0x1.95f310eafbaddp-34, 0.0},
+    {0x1.661ec6a5122f9p+0, -0x1.57bf753c00000p-2, -0x1.1a3f5b5bdcba8p-35, 0.0},
+    {0x1.642c8590b2164p+0, -0x1.522ae07400000p-2, 0x1.d70a2c7bf4d9cp-36, 0.0},
+    {0x1.623fa77016240p+0, -0x1.4c9e09e000000p-2, -0x1.72c3ceedc9ea5p-34, 0.0},
+    {0x1.6058160581606p+0, -0x1.4718dc2800000p-2, 0x1.c77c7138259f6p-35, 0.0},
+    {0x1.5e75bb8d015e7p+0, -0x1.419b423c00000p-2, -0x1.5e8c615b76487p-34, 0.0},
+    {0x1.5c9882b931057p+0, -0x1.3c25277400000p-2, 0x1.99cf975693f28p-35, 0.0},
+    {0x1.5ac056b015ac0p+0, -0x1.36b6776c00000p-2, 0x1.eeea1324f0e88p-38, 0.0},
+    {0x1.58ed2308158edp+0, -0x1.314f1e1c00000p-2, -0x1.35ce348a59bd8p-34, 0.0},
+    {0x1.571ed3c506b3ap+0, -0x1.2bef07cc00000p-2, -0x1.c9354b7494a01p-34, 0.0},
+    {0x1.5555555555555p+0, -0x1.2696211400000p-2, 0x1.648dd0f882913p-35, 0.0},
+    {0x1.5390948f40febp+0, -0x1.214456d000000p-2, -0x1.d71a9d5eba46cp-35, 0.0},
+    {0x1.51d07eae2f815p+0, -0x1.1bf9963400000p-2, -0x1.a6b9485aa28f8p-34, 0.0},
+    {0x1.5015015015015p+0, -0x1.16b5ccbc00000p-2, 0x1.3048caa410b5dp-34, 0.0},
+    {0x1.4e5e0a72f0539p+0, -0x1.1178e82400000p-2, 0x1.81b8591cc74bep-34, 0.0},
+    {0x1.4cab88725af6ep+0, -0x1.0c42d67800000p-2, 0x1.e9d1e569d3863p-34, 0.0},
+    {0x1.4afd6a052bf5bp+0, -0x1.0713860400000p-2, -0x1.ab0c7f6d8b76ap-35, 0.0},
+    {0x1.49539e3b2d067p+0, -0x1.01eae56400000p-2, 0x1.9396ec4c1485fp-34, 0.0},
+    {0x1.47ae147ae147bp+0, -0x1.f991c6c800000p-3, -0x1.9d9bd1ecca0cep-34, 0.0},
+    {0x1.460cbc7f5cf9ap+0, -0x1.ef5ade5000000p-3, 0x1.1800d688ab2dep-34, 0.0},
+    {0x1.446f86562d9fbp+0, -0x1.e530f00000000p-3, 0x1.8efed7dd89fbep-35, 0.0},
+    {0x1.42d6625d51f87p+0, -0x1.db13db1000000p-3, 0x1.5bb5fb15ee2b6p-34, 0.0},
+    {0x1.4141414141414p+0, -0x1.d1037f2800000p-3, 0x1.aa18527e75b6fp-35, 0.0},
+    {0x1.3fb013fb013fbp+0, -0x1.c6ffbc7000000p-3, 0x1.fe11ed72c5963p-36, 0.0},
+    {0x1.3e22cbce4a902p+0, -0x1.bd08738000000p-3, -0x1.dec54f774d57ep-34, 0.0},
+    {0x1.3c995a47babe7p+0, -0x1.b31d857800000p-3, 0x1.218e2886a7567p-34, 0.0},
+    {0x1.3b13b13b13b14p+0, -0x1.a93ed3c800000p-3, -0x1.5b3cade57d4efp-36, 0.0},
+    {0x1.3991c2c187f63p+0, -0x1.9f6c407000000p-3, -0x1.12cc556b432c1p-36, 0.0},
+    {0x1.3813813813814p+0, -0x1.95a5add000000p-3, 0x1.1fcfb3af4ebe0p-36, 0.0},
+    {0x1.3698df3de0748p+0, -0x1.8beafeb000000p-3, -0x1.c7f47755aa8b7p-34, 0.0},
+    {0x1.3521cfb2b78c1p+0, -0x1.823c165800000p-3, 0x1.72e1fd24659cep-34, 0.0},
+    {0x1.33ae45b57bcb2p+0, -0x1.7898d85800000p-3, 0x1.dd9c5f9070914p-34, 0.0},
+    {0x1.323e34a2b10bfp+0, -0x1.6f0128b800000p-3, 0x1.52a8e26f2ce11p-36, 0.0},
+    {0x1.30d190130d190p+0, -0x1.6574ebe800000p-3, -0x1.82672e2cb0f0cp-36, 0.0},
+    {0x1.2f684bda12f68p+0, -0x1.5bf406b800000p-3, 0x1.5e128023eb68ap-34, 0.0},
+    {0x1.2e025c04b8097p+0, -0x1.527e5e4800000p-3, -0x1.0dac6791cad30p-34, 0.0},
+    {0x1.2c9fb4d812ca0p+0, -0x1.4913d83000000p-3, -0x1.9dab16f2a9fb7p-34, 0.0},
+    {0x1.2b404ad012b40p+0, -0x1.3fb45a5800000p-3, -0x1.928c989e06573p-35, 0.0},
+    {0x1.29e4129e4129ep+0, -0x1.365fcb0000000p-3, -0x1.590146fa8234bp-35, 0.0},
+    {0x1.288b01288b013p+0, -0x1.2d1610c800000p-3, -0x1.a04f43b32e06dp-37, 0.0},
+    {0x1.27350b8812735p+0, -0x1.23d712a800000p-3, 0x1.b1eff55c702c2p-34, 0.0},
+    {0x1.25e22708092f1p+0, -0x1.1aa2b7e000000p-3, -0x1.1fb94adc88713p-34, 0.0},
+    {0x1.2492492492492p+0, -0x1.1178e82000000p-3, -0x1.3f23cef19c5a1p-34, 0.0},
+    {0x1.23456789abcdfp+0, -0x1.08598b5800000p-3, -0x1.e3a0680a3fd9cp-35, 0.0},
+    {0x1.21fb78121fb78p+0, -0x1.fe8913a000000p-4, 0x1.2154db593e843p-35, 0.0},
+    {0x1.20b470c67c0d9p+0, -0x1.ec73983000000p-4, -0x1.4224cf75019bap-37, 0.0},
+    {0x1.1f7047dc11f70p+0, -0x1.da72764000000p-4, 0x1.eee586bfe058fp-34, 0.0},
+    {0x1.1e2ef3b3fb874p+0, -0x1.c885802000000p-4, 0x1.0ed3815c734aap-34, 0.0},
+    {0x1.1cf06ada2811dp+0, -0x1.b6ac88e000000p-4, 0x1.4a938d002bf77p-34, 0.0},
+    {0x1.1bb4a4046ed29p+0, -0x1.a4e7641000000p-4, 0x1.390f219b5ca20p-34, 0.0},
+    {0x1.1a7b9611a7b96p+0, -0x1.9335e5d000000p-4, -0x1.65261eb8757a9p-34, 0.0},
+    {0x1.19453808ca29cp+0, -0x1.8197e2f000000p-4, -0x1.038fbf6e7cb80p-34, 0.0},
+    {0x1.1811811811812p+0, -0x1.700d30b000000p-4, 0x1.53f17cb92b311p-36, 0.0},
+    {0x1.16e0689427379p+0, -0x1.5e95a4e000000p-4, 0x1.a1b8cd4c78ba4p-34, 0.0},
+    {0x1.15b1e5f75270dp+0, -0x1.4d3115d000000p-4, -0x1.03f560ed3e859p-35, 0.0},
+    {0x1.1485f0e0acd3bp+0, -0x1.3bdf5a8000000p-4, 0x1.708d0f056892cp-35, 0.0},
+    {0x1.135c81135c811p+0, -0x1.2aa04a4000000p-4, -0x1.1c5e85aea2c73p-34, 0.0},
+    {0x1.12358e75d3033p+0, -0x1.1973bd1000000p-4, -0x1.1955828553e4cp-34, 0.0},
+    {0x1.1111111111111p+0, -0x1.08598b6000000p-4, 0x1.8717e9dd70099p-34, 0.0},
+    {0x1.0fef010fef011p+0, -0x1.eea31c0000000p-5, -0x1.ae1ef41b036c5p-39, 0.0},
+    {0x1.0ecf56be69c90p+0, -0x1.ccb73ce000000p-5, 0x1.126983c91f60ap-36, 0.0},
+    {0x1.0db20a88f4696p+0, -0x1.aaef2d0000000p-5, -0x1.f62210b46a777p-34, 0.0},
+    {0x1.0c9714fbcda3bp+0, -0x1.894aa14000000p-5, -0x1.3f66956a2fa5ep-34, 0.0},
+    {0x1.0b7e6ec259dc8p+0, -0x1.67c94f2000000p-5, -0x1.a976ca8209f33p-34, 0.0},
+    {0x1.0a6810a6810a7p+0, -0x1.466aed4000000p-5, -0x1.6f1fc66452101p-36, 0.0},
+    {0x1.0953f39010954p+0, -0x1.252f330000000p-5, 0x1.cb9eff947f792p-35, 0.0},
+    {0x1.0842108421084p+0, -0x1.0415d8a000000p-5, 0x1.8bbbf8fe8c38ap-37, 0.0},
+    {0x1.073260a47f7c6p+0, -0x1.c63d2ec000000p-6, -0x1.4aad70c7f3d66p-38, 0.0},
+    {0x1.0624dd2f1a9fcp+0, -0x1.8492528000000p-6, -0x1.919589173697dp-35, 0.0},
+    {0x1.05197f7d73404p+0, -0x1.432a924000000p-6, -0x1.980cbb9cc9432p-34, 0.0},
+    {0x1.0410410410410p+0, -0x1.0205658000000p-6, -0x1.26b06e93e4742p-35, 0.0},
+    {0x1.03091b51f5e1ap+0, -0x1.82448a0000000p-7, -0x1.c45141904b161p-34, 0.0},
+    {0x1.0204081020408p+0, -0x1.0101578000000p-7, 0x1.3b90cb6b999d3p-34, 0.0},
+    {0x1.0101010101010p+0, -0x1.0080560000000p-8, 0x1.a9dd36a0699c7p-34, 0.0},
+    {0x1.0000000000000p+0, 0x0.0p+0, 0x0.0p+0, 0.0}};
+__shared__ __attribute__((aligned(32))) double lds_logtab[129][4];
+
 // Every kernel that evaluates the per-lane code calls this first, with all
 // threads of the block (it ends with a barrier).
-__device__ inline void stage_exp_table() {
+__device__ inline void stage_tables() {
   if (threadIdx.x < 32) lds_exp2j32[threadIdx.x] = kExp2j32[threadIdx.x];
+  for (unsigned i = threadIdx.x; i < 129u * 4u; i += blockDim.x)
+    (&lds_logtab[0][0])[i] = (&kLogTab[0][0])[i];
   __syncthreads();
 }
 
@@ -119,13 +262,31 @@ __device__ inline double fexp(double x) {
   return __builtin_ldexp(fma(t, q, t), ni >> 5);
 }
 
+__device__ inline double flog(double x) {
+  const double m = __builtin_amdgcn_frexp_mant(x);
+  const int e = __builtin_amdgcn_frexp_exp(x);
+  const int j = int(__builtin_rint(fma(m, 256.0, -128.0)));
+  const double* t = lds_logtab[j];
+  const double r = fma(m, t[0], -1.0);
+  double q = fma(r, 1.0 / 7.0, -1.0 / 6.0);
+  q = fma(r, q, 1.0 / 5.0);
+  q = fma(r, q, -0.25);
+  q = fma(r, q, 1.0 / 3.0);
+  q = fma(r, q, -0.5);
+  const double p = fma(r * r, q, r);
+  const double de = double(e);
+  const double hi = fma(de, 0x1.62e42ff000000p-1, t[1]);  // ln 2 on the 2^-32 grid
+  const double lo = fma(de, -0x1.718432a1b0e26p-35, t[2]);
+  return hi + (lo + p);
+}
+
 template <class R>
 struct Mth;
 template <>
 struct Mth<double> {
   __device__ static double ea(double x) { return fexp(x); }
   __device__ static double ex(double x) { return fexp(x); }
-  __device__ static double lg(double x) { return log(x); }
+  __device__ static double lg(double x) { return flog(x); }
   // every root and quotient in the assembly has a positive, normal argument
   // (temperatures are clamped to [1, 1e8] K or floored at T_CMB)
   __device__ static double sq(double x) { return fsqrt(x); }
@@ -266,7 +427,7 @@ __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, d
   if (Tc > 1.0e8) { Tc = 1.0e8; clampT = R(0); }
   const double T64 = Tc;
   const double iT64 = frcp(Tc);
-  const double lnT64 = log(Tc);
+  const double lnT64 = flog(Tc);
   const R T = R(T64);
   const R n = R(ck.n);
   const R iT = R(iT64);
@@ -516,7 +677,7 @@ __device__ inline double hm_ratio(const Net& nt, double Tin) {
   using M = Mth<R>;
   const double Tc = Tin < 1.0 ? 1.0 : (Tin > 1.0e8 ? 1.0e8 : Tin);
   TF<R> k2, k3;
-  k2k3<R>(Tc, log(Tc), 1.0 / Tc, k2, k3);
+  k2k3<R>(Tc, flog(Tc), 1.0 / Tc, k2, k3);
   const R a = R(nt.rm[2]) * k2.v, b = R(nt.rm[3]) * k3.v;
   return b > R(0) ? double(a * M::dv(R(1), b)) : 0.0;
 }

@@ -26,7 +26,7 @@ constexpr unsigned kStash = 64;
 template <class R, bool kNR>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 void li_step_kernel(Args) {
-  stage_exp_table();
+  stage_tables();
   const int lane = threadIdx.x & 63;
   int64_t cell = -1;
   Lane L;

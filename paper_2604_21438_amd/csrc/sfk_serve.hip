@@ -173,7 +173,7 @@ __device__ inline void set_level_prio(int lvl, int& prio) {
 // waves take the freed slots, serves all new work.
 template <class R>
 __global__ __launch_bounds__(kBlock) void served_drain_kernel(ServedArgs) {
-  stage_exp_table();
+  stage_tables();
   const int lane = threadIdx.x & 63;
   int64_t cell = -1;
   uint64_t tk = 0, pend = 0;  // the lane's request token; pend = tk + 1 once stored
