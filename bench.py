@@ -43,8 +43,8 @@ BYTES_PER_CELL = 132          # 8 float64 reads, 7 float64 writes, 3 int32 write
 # (bench.py --calibrate-copy 256).  Valid only for the plain-step sources
 # whose combined SHA-1 is given (sfk.h, sfk_lane.h, sfk_li.hip, in that
 # order): with any other source the figure is reported as null.
-TRAFFIC = {"kernel_sha1": "d11c283abba5b67d7772efb2beab3106cfe7d3d8",
-           "fetch_bytes": 2.9442e9, "write_bytes": 9.0975e8}
+TRAFFIC = {"kernel_sha1": "3c38136b4f318e7ec0848969acf02fed4ab6bc77",
+           "fetch_bytes": 2.9282e9, "write_bytes": 9.0980e8}
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2604_21438_amd", "csrc", f)
                for f in ("sfk.h", "sfk_lane.h", "sfk_li.hip")]
 
