@@ -250,7 +250,10 @@ class Context:
                tag: int = 0, sync: bool = True) -> int:
         """Queue a request; the tensors are updated in place once poll()
         reports it done.  The library reads them on its own stream, so by
-        default torch's current stream is synchronised first."""
+        default torch's current stream is synchronised first.  `level` is
+        the AMR level: waves holding cells of finer levels issue first, and
+        with SFC_SERVE_LEVEL_CLAIMS=1 (read when the context is created)
+        finer levels are also handed out first."""
         import torch
         if sync:
             torch.cuda.current_stream(self.device).synchronize()
