@@ -223,7 +223,9 @@ def test_served_level_claims_take_finer_level_first():
     print(f"[served] fine/coarse latency: level claims {f_lvl * 1e3:.1f}/{c_lvl * 1e3:.1f} ms, "
           f"admission order {f_adm * 1e3:.1f}/{c_adm * 1e3:.1f} ms", flush=True)
     assert f_lvl < c_lvl
-    assert f_lvl < 0.5 * f_adm
+    # measured 16-17 ms against 86-102 ms; the bound leaves room for host
+    # scheduling noise in either run
+    assert f_lvl < 0.7 * f_adm
 
 
 def test_served_amr_chain_matches_plain():
