@@ -83,6 +83,21 @@ def test_fp64_hii_region():
         _check_fp64(cells, dt, factor, label=f"H II stand-in factor {factor:g}")
 
 
+def test_fp64_full_temperature_range():
+    """Gas temperatures over the whole range the rate fits accept (1 K to
+    1e8 K, log-uniform) and dust from 3 K to 1e3 K: the Boltzmann factors
+    underflow at the cold end and ln(1 - e^(-6000/T)) nears its small
+    argument at the hot end, so the kernels' own exp and ln are exercised
+    over their full range of arguments."""
+    cells = W.uniform_population(2048, seed_offset=31)
+    rng = np.random.default_rng(31)
+    tg = 10.0 ** rng.uniform(0.0, 8.0, 2048)
+    td = 10.0 ** rng.uniform(np.log10(3.0), 3.0, 2048)
+    cells["eint"] = W.internal_energy(cells["nh"], cells["y_h2"], cells["y_e"], tg)
+    cells["tdust"] = td
+    _check_fp64(cells, 3.15576e10, label="1 K - 1e8 K")
+
+
 def test_fp64_evolve_ir():
     """IR energy density evolved with the dust (Appendix C 3x3 system)."""
     cells, dt = W.small_cells()
