@@ -92,6 +92,13 @@ def report(errs, exc, n, label="", gpu=None, ref=None, cells=None):
 FP64_TOL = 1e-9
 WELL_CONDITIONED = 1e-12
 SPREAD_FACTOR = 1000.0
+# y_H is not solved for: H-nuclei conservation defines it as
+# 1 - 2 y_H2 - y_H+ - y_H-, a difference of terms up to 1, so binary64
+# determines it only to a few units in the last place of 1 in absolute
+# terms.  In a nearly fully ionised or molecular cell (y_H ~ 1e-9) one such
+# unit is a 1e-8 relative change, which no other rounding order can avoid;
+# the binary64 bar therefore accepts |dy_H| within YH_ABS.
+YH_ABS = 4.0 * np.finfo(float).eps
 
 
 def worst_of(errs, n):
@@ -105,10 +112,12 @@ def assert_fp64_parity(gpu, cells, dt, onet, opar, label=""):
     """The binary64 bar: cells the reference determines to 1e-12 (rounding
     spread over three other valid roundings of the reference) match to
     1e-9 with identical subcycle counts and flags; the others match to
-    max(1e-9, 1000 x spread).  Returns the reference outputs."""
+    max(1e-9, 1000 x spread); y_H deviations within YH_ABS (absolute) count
+    as exact.  Returns the reference outputs."""
     ref = run_oracle(cells, dt, onet, opar)
     spread = oracle.rounding_spread(cells, dt, ref, onet, opar, host_threads())
     errs, exc = compare(gpu, ref)
+    errs["y_h"] = np.where(np.abs(gpu["y_h"] - ref["y_h"]) <= YH_ABS, 0.0, errs["y_h"])
     n = cells["nh"].shape[0]
     report(errs, exc, n, label, gpu, ref, cells)
     worst = worst_of(errs, n)
