@@ -98,6 +98,35 @@ def test_fp64_full_temperature_range():
     _check_fp64(cells, 3.15576e10, label="1 K - 1e8 K")
 
 
+def test_mixed_full_temperature_range():
+    """The mixed path on the same 1 K - 1e8 K cells: binary32 assembly
+    stays finite (powers of T up to T^3.8 ~ 1e30 and the Boltzmann factors
+    are inside or flushed below the binary32 range), conservation holds in
+    the binary64 update, and the median bar holds for every output."""
+    sfc = _sfc()
+    cells = W.uniform_population(2048, seed_offset=31)
+    rng = np.random.default_rng(31)
+    tg = 10.0 ** rng.uniform(0.0, 8.0, 2048)
+    td = 10.0 ** rng.uniform(np.log10(3.0), 3.0, 2048)
+    cells["eint"] = W.internal_energy(cells["nh"], cells["y_h2"], cells["y_e"], tg)
+    cells["tdust"] = td
+    net = sfc.default_network()
+    par = sfc.default_params()
+    gpu = run_gpu(cells, 3.15576e10, sfc.MIXED, 1.0, net, par, label="mixed 1 K - 1e8 K")
+    for k in ("y_h2", "y_e", "y_h", "y_hp", "y_hm", "tgas", "tdust", "eint"):
+        assert np.all(np.isfinite(gpu[k])), k
+    onet, opar = oracle_net_params(net, par, 1.0)
+    ref = run_oracle(cells, 3.15576e10, onet, opar)
+    errs, exc = compare(gpu, ref)
+    report(errs, exc, 2048, "mixed 1 K - 1e8 K", gpu, ref, cells)
+    for k, e in errs.items():
+        print(f"[mixed 1 K - 1e8 K] {k}: median {np.median(e):.2e} p99 {np.percentile(e, 99):.2e} "
+              f"max {np.max(e):.2e}", flush=True)
+        assert np.median(e) <= MIXED_TOL, (k, float(np.median(e)))
+    s = gpu["y_h"] + 2 * gpu["y_h2"] + gpu["y_hp"] + gpu["y_hm"]
+    assert np.all(np.abs(s - 1) <= 8 * np.finfo(float).eps)
+
+
 def test_fp64_evolve_ir():
     """IR energy density evolved with the dust (Appendix C 3x3 system)."""
     cells, dt = W.small_cells()
