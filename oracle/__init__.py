@@ -103,9 +103,18 @@ _libs: dict = {}
 
 
 def _lib(counting: bool = False, variant: str = "plain"):
-    path = LIB_COUNT if counting else {"fma": LIB_FMA, "dn": LIB_DN}.get(variant, LIB)
+    """The plain build, or a named variant ("fma", "dn"), or any other
+    build of the same source given by its path (the pins' mutation test
+    builds copies with planted mistakes)."""
+    if variant.endswith(".so"):
+        path = variant
+    else:
+        path = LIB_COUNT if counting else {"fma": LIB_FMA, "dn": LIB_DN}.get(variant, LIB)
     if path not in _libs:
-        if not os.path.exists(path):
+        if variant.endswith(".so"):
+            if not os.path.exists(path):
+                raise FileNotFoundError(path)
+        elif not os.path.exists(path):
             build(force=False)
         lib = C.CDLL(path)
         P = C.POINTER

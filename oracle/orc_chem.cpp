@@ -33,7 +33,13 @@
  * equilibrium y_H ~ 2e-5, alpha_B, H2 formation time), closed-form
  * transients and equilibria, conservation to round-off, the Appendix C
  * energy identity, derivative checks against central differences,
- * first-order convergence to RK4, LI/NR agreement at equilibrium.
+ * first-order convergence to RK4, LI/NR agreement at equilibrium.  The
+ * tight gas-dust step (dust_tight_step) has its own: first-order
+ * convergence to RK4 with every subcycle tight, energy conservation of a
+ * single tight step, quick Newton convergence in strongly coupled cells,
+ * and radiative equilibrium in the infinite-step limit; a mutation test
+ * builds copies of this file with planted mistakes in that step and
+ * checks that each one fails at least one of those pins.
  * Parity unpinned: the full-network trajectories with the stand-in physics
  * (nothing outside the oracle fixes them).
  */

@@ -448,6 +448,32 @@ def test_li_first_order_convergence_with_dust():
     del tc4
 
 
+# ------------------------------------------------ tight gas-dust coupling
+# (Sec. 2 "Time stepping": iterations only where gas and grains are tightly
+# coupled; Appendix C).  The checks live in tight_pins.py so that the
+# mutation test can run them on builds with planted mistakes.
+
+@pytest.mark.parametrize("ir_mode", [oracle.IR_FIXED, oracle.IR_EVOLVE])
+def test_tight_dust_first_order_convergence_to_rk4(ir_mode):
+    import tight_pins
+    tight_pins.check_convergence(ir_mode)
+
+
+def test_tight_dust_step_conserves_energy():
+    import tight_pins
+    tight_pins.check_energy_identity()
+
+
+def test_tight_dust_newton_converges_quickly():
+    import tight_pins
+    tight_pins.check_newton()
+
+
+def test_tight_dust_infinite_step_is_radiative_equilibrium():
+    import tight_pins
+    tight_pins.check_steady_state()
+
+
 def _equilibrium_cells():
     return cell_dict([30.0, 300.0, 3000.0], [100.0, 3000.0, 50.0], [20.0, 20.0, 20.0],
                      [0.3, 1e-3, 0.4], [1e-4, 1e-3, 1e-5], n_euv=[0.0, 0.0, 0.0],
