@@ -6,12 +6,18 @@ the CPU-baseline leg of ``bench.py`` may import this package.  It shares no
 code with the HIP implementation in ``paper_2604_21438_amd``.
 
 The arithmetic lives in ``orc_chem.cpp`` (plain serial C++, binary64,
--ffp-contract=off).  ``build()`` compiles four libraries next to this
+-ffp-contract=off).  ``build()`` compiles eight libraries next to this
 file: ``liborc.so`` (the reference), ``liborc_count.so`` (counting build,
 algorithmic operation count per cell-update), ``liborc_fma.so`` and
 ``liborc_dn.so`` (other valid roundings: contracted multiply-adds and
-transcendentals nudged up / uncontracted and nudged down, used only to
-measure each cell's conditioning).
+transcendentals nudged up / uncontracted and nudged down),
+``liborc_rcp.so`` / ``liborc_rcpdn.so`` (every quotient formed as a
+product with a reciprocal moved one ulp up, contracted / down,
+uncontracted), ``liborc_all.so`` (all of these classes at once) and
+``liborc_c32.so`` (exponentials and powers rounded to binary32).  The six
+alternative builds only measure each cell's
+conditioning: to binary64 rounding, and to coefficients of binary32
+accuracy.
 """
 from __future__ import annotations
 
@@ -31,6 +37,16 @@ LIB_FMA = os.path.join(HERE, "liborc_fma.so")
 # and a third: no contraction, transcendentals nudged down, powers formed
 # as exp(y log x)
 LIB_DN = os.path.join(HERE, "liborc_dn.so")
+# and two more in the rounding class of division through a refined
+# hardware reciprocal: a / b = a * rcp(b), the reciprocal one ulp up with
+# contraction, or one ulp down without
+LIB_RCP = os.path.join(HERE, "liborc_rcp.so")
+LIB_RCPDN = os.path.join(HERE, "liborc_rcpdn.so")
+# every class at once: contraction, transcendentals and reciprocals one ulp up
+LIB_ALL = os.path.join(HERE, "liborc_all.so")
+# exponentials and powers rounded to binary32, everything else binary64:
+# the error floor of binary32 rate coefficients (mixed-precision bar)
+LIB_C32 = os.path.join(HERE, "liborc_c32.so")
 SRC = os.path.join(HERE, "orc_chem.cpp")
 
 NREAC, NPROC, NLINE = 12, 14, 5
@@ -47,7 +63,11 @@ def build(force: bool = True) -> None:
     """Compile the plain, counting and contracted oracle libraries (g++)."""
     variants = ((LIB, []), (LIB_COUNT, ["-DORC_COUNT"]),
                 (LIB_FMA, ["-mfma", "-ffp-contract=fast", "-DORC_NUDGE"]),
-                (LIB_DN, ["-DORC_NUDGE", "-DORC_NUDGE_DOWN"]))
+                (LIB_DN, ["-DORC_NUDGE", "-DORC_NUDGE_DOWN"]),
+                (LIB_RCP, ["-DORC_RCP", "-mfma", "-ffp-contract=fast"]),
+                (LIB_RCPDN, ["-DORC_RCP", "-DORC_NUDGE_DOWN"]),
+                (LIB_ALL, ["-DORC_RCP", "-DORC_NUDGE", "-mfma", "-ffp-contract=fast"]),
+                (LIB_C32, ["-DORC_COEF32"]))
     for out, extra in variants:
         if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(SRC):
             continue
@@ -103,13 +123,16 @@ _libs: dict = {}
 
 
 def _lib(counting: bool = False, variant: str = "plain"):
-    """The plain build, or a named variant ("fma", "dn"), or any other
+    """The plain build, or a named rounding variant ("fma", "dn", "rcp",
+    "rcpdn", "all", "c32"), or any other
     build of the same source given by its path (the pins' mutation test
     builds copies with planted mistakes)."""
     if variant.endswith(".so"):
         path = variant
     else:
-        path = LIB_COUNT if counting else {"fma": LIB_FMA, "dn": LIB_DN}.get(variant, LIB)
+        path = LIB_COUNT if counting else {"fma": LIB_FMA, "dn": LIB_DN, "rcp": LIB_RCP,
+                                       "rcpdn": LIB_RCPDN, "all": LIB_ALL,
+                                       "c32": LIB_C32}.get(variant, LIB)
     if path not in _libs:
         if variant.endswith(".so"):
             if not os.path.exists(path):
@@ -207,7 +230,8 @@ def _prepare(cells: dict, ir_mode: int):
 def li_step(cells: dict, dt: float, net: Network | None = None, params: Params | None = None,
             nthreads: int = 1, variant: str = "plain") -> dict:
     """LI update of every cell over dt [s]; returns a new dict of arrays.
-    variant "fma" runs the build with multiply-add contraction."""
+    variant names another rounding of the same arithmetic ("fma", "dn",
+    "rcp", "rcpdn", "all", "c32"; see build)."""
     net = net or default_network()
     params = params or default_params()
     out, n = _prepare(cells, params.ir_mode)
@@ -314,23 +338,29 @@ def _rel(a, b, floor=1e-20):
 def rounding_spread(cells: dict, dt: float, ref: dict, net=None, params=None,
                     nthreads: int = 1, method: str = "li") -> np.ndarray:
     """Per cell, the largest relative change of any output between the
-    reference result `ref` and three other valid roundings of the same
-    computation: the contracted build with transcendentals nudged up, the
+    reference result `ref` and seven other valid roundings of the same
+    computation: the contracted build with transcendentals nudged up; the
     uncontracted build with them nudged down and powers formed as
-    exp(y log x), and the input internal
-    energy moved by one unit in the last place.  A cell whose spread exceeds a
-    tolerance is not determined to that tolerance by binary64 arithmetic."""
+    exp(y log x); quotients formed through a reciprocal moved one ulp up
+    (contracted) or down (uncontracted); all of the first kinds at once
+    (contracted, transcendentals and reciprocals one ulp up); and the input
+    internal energy moved by one unit in the last place either way.  A cell whose spread exceeds a
+    tolerance is not determined to that tolerance by binary64 arithmetic.
+    Cells that the reference marks invalid (NaN outputs) have spread 0 here;
+    comparisons treat them separately."""
     params = params or default_params()
     step = li_step if method == "li" else nr_step
-    alt = [step(cells, dt, net, params, nthreads, variant="fma"),
-           step(cells, dt, net, params, nthreads, variant="dn")]
-    nudged = dict(cells)
-    nudged["eint"] = np.nextafter(np.asarray(cells["eint"], np.float64), np.inf)
-    alt.append(step(nudged, dt, net, params, nthreads))
+    alt = [step(cells, dt, net, params, nthreads, variant=v)
+           for v in ("fma", "dn", "rcp", "rcpdn", "all")]
+    for direction in (np.inf, -np.inf):
+        nudged = dict(cells)
+        nudged["eint"] = np.nextafter(np.asarray(cells["eint"], np.float64), direction)
+        alt.append(step(nudged, dt, net, params, nthreads))
     spread = np.zeros(ref["nsub"].shape[0])
+    invalid = (np.asarray(ref["flags"]) & F_INVALID) != 0
     for o in alt:
         for k in OUT_KEYS:
-            spread = np.maximum(spread, _rel(o[k], ref[k]))
+            spread = np.maximum(spread, np.where(invalid, 0.0, _rel(o[k], ref[k])))
     return spread
 
 
@@ -344,6 +374,22 @@ def step_sensitivity(cells: dict, dt: float, ref: dict, net=None, params=None,
     p2.f_chem = params.f_chem * (1.0 + eps)
     o = li_step(cells, dt, net, p2, nthreads)
     s = np.zeros(ref["nsub"].shape[0])
+    invalid = (np.asarray(ref["flags"]) & F_INVALID) != 0
     for k in OUT_KEYS:
-        s = np.maximum(s, _rel(o[k], ref[k]))
+        s = np.maximum(s, np.where(invalid, 0.0, _rel(o[k], ref[k])))
+    return s
+
+
+def coefficient_sensitivity(cells: dict, dt: float, ref: dict, net=None, params=None,
+                            nthreads: int = 1) -> np.ndarray:
+    """Per cell, the largest relative output change when every exponential
+    and power of the reference (its rate, cooling and opacity coefficients)
+    is rounded to binary32: how far coefficients of binary32 accuracy alone
+    move the result.  Invalid cells get 0."""
+    params = params or default_params()
+    o = li_step(cells, dt, net, params, nthreads, variant="c32")
+    s = np.zeros(ref["nsub"].shape[0])
+    invalid = (np.asarray(ref["flags"]) & F_INVALID) != 0
+    for k in OUT_KEYS:
+        s = np.maximum(s, np.where(invalid, 0.0, _rel(o[k], ref[k])))
     return s

@@ -388,9 +388,21 @@ __device__ inline void k2k3(double T, double lnT, double iT, TF<R>& k2, TF<R>& k
 
 template <class R>
 struct Chem {
-  R f[3];        // R_H2, R_e [1/s], Q/(k_B n_H) [K/s]
+  double f[3];   // R_H2, R_e [1/s], Q/(k_B n_H) [K/s]
   R J[3][3];     // d f_i / d (y_H2, y_e, T) at fixed others
   R ratio;       // k_H2 / k_H3 (steady-state y_H- / y_e)
+};
+
+// Accumulator of a net source (R_H2, R_e, Q): value in binary64 in both
+// precisions, partials in R.  A net source near balance is a small
+// difference of large formation and destruction (heating and cooling)
+// terms; summed in binary32 its relative error would be eps_32 times
+// gross / net, and the step-size control, which divides abundances and
+// energy by these net sources, would follow that rounding noise.
+template <class R>
+struct Acc {
+  double v;
+  R a, e, t;
 };
 
 // Per-cell constants that do not change during a call.
@@ -406,6 +418,16 @@ template <class R>
 __device__ inline void acc(G<R>& A, R s, TF<R> k, G<R> x) {
   const R kv = s * k.v, kt = s * k.t;
   A.v = A.v + kv * x.v;
+  A.a = A.a + kv * x.a;
+  A.e = A.e + kv * x.e;
+  A.t = A.t + (kt * x.v + kv * x.t);
+}
+// the same into a net-source accumulator: each term rounded in R, the sum
+// in binary64 (for R = double the arithmetic of the overload above)
+template <class R>
+__device__ inline void acc(Acc<R>& A, R s, TF<R> k, G<R> x) {
+  const R kv = s * k.v, kt = s * k.t;
+  A.v = A.v + double(kv) * double(x.v);
   A.a = A.a + kv * x.a;
   A.e = A.e + kv * x.e;
   A.t = A.t + (kt * x.v + kv * x.t);
@@ -462,7 +484,7 @@ __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, d
   const G<R> YH{R(yh_d), R(-2), R(-1) - R(2) * ratio, R(-2) * dratio * ye};
   const G<R> HE = YH * YE;
 
-  G<R> rh2{R(0), R(0), R(0), R(0)}, re = rh2, q = rh2;
+  Acc<R> rh2{0.0, R(0), R(0), R(0)}, re = rh2, q = rh2;
   const R evn = R(EVK) * n;  // eV / k_B * n_H
 
   // H2 (through the H- channel, H3): net H2 formation k_H2 n y_H y_e;
@@ -581,7 +603,7 @@ __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, d
     acc(rh2, -k10, TF<R>{R(1), R(0)}, Y2);
     acc(q, R(nt.pm[1] * nt.g2k) * k9, TF<R>{R(1), R(0)}, YH);
     acc(q, R(nt.pm[2] * nt.g3k) * k10, TF<R>{R(1), R(0)}, Y2);
-    q.v = q.v + R(ck.g4);
+    q.v = q.v + ck.g4;
   }
   // Lambda_7, recombination cooling fit in log10 T (10^P / k_B)
   {
@@ -656,7 +678,7 @@ __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, d
       const G<R> frac = quot(clu, den);
       const G<R> e = emit * frac;
       const R w = m13 * R(nt.l_tul[j] * nt.l_a[j]);
-      q.v = q.v + w * e.v;
+      q.v = q.v + double(w) * double(e.v);
       q.a = q.a + w * e.a;
       q.e = q.e + w * e.e;
       q.t = q.t + w * e.t;
@@ -840,7 +862,7 @@ __device__ inline void renormalise(const Net& nt, const Par& pr, Lane& L, bool i
   const double yh_lo = 1.0 - 2.0 * L.y2 - L.ye - 2.0 * pr.hm_ratio_max * L.ye;
   if (!(yh_lo >= 0.0)) {
     const double T = iso ? L.Tiso : L.E / (knb * cvk(pr, L.y2, L.ye));
-    const double r = hm_ratio<R>(nt, T);
+    const double r = hm_ratio<double>(nt, T);
     const double yhm = r * L.ye;
     const double yhp = L.ye + yhm;
     const double yh = 1.0 - 2.0 * L.y2 - yhp - yhm;
@@ -902,8 +924,8 @@ __device__ inline void dust_tight(const Net& nt, const Par& pr, Lane& L, double 
   const double knb = KB * L.ck.n;
   const double cv = knb * cvk(pr, L.y2, L.ye);
   const double Tg0 = L.E * frcp(cv);
-  Dust<R> d;
-  dust_eval<R>(nt, pr, Tg0, L.Td, L.Eir, L.ck, d);
+  Dust<double> d;
+  dust_eval<double>(nt, pr, Tg0, L.Td, L.Eir, L.ck, d);
   TightC t;
   t.td0 = L.Td;
   t.tg0 = Tg0;
@@ -980,8 +1002,8 @@ __device__ inline void dust_linear(const Net& nt, const Par& pr, Lane& L, double
   const double knb = KB * L.ck.n;
   const double cv = knb * cvk(pr, L.y2, L.ye);
   const double Tg = L.E * frcp(cv);
-  Dust<R> d;
-  dust_eval<R>(nt, pr, Tg, L.Td, L.Eir, L.ck, d);
+  Dust<double> d;
+  dust_eval<double>(nt, pr, Tg, L.Td, L.Eir, L.ck, d);
   const double ctil = pr.c_red * CL;
   const double ac = ARAD * CL;
   const double G = double(d.G), gd = double(d.gd), zeta = double(d.zeta);
@@ -1049,8 +1071,8 @@ __device__ bool subcycle(const Net& nt, const Par& pr, Lane& L) {
 
   double nu_dust = 0.0, qgg = 0.0;
   if (dust_on) {
-    Dust<R> d;
-    dust_eval<R>(nt, pr, T, L.Td, L.Eir, L.ck, d);
+    Dust<double> d;
+    dust_eval<double>(nt, pr, T, L.Td, L.Eir, L.ck, d);
     // gas-grain exchange rho S_g / (k_B n) [K/s]
     qgg = double(d.Sg) * (L.ck.rho / knb);
     const double alpha = knb * (ntr * pr.igm1) * frcp(L.ck.rho);
@@ -1416,7 +1438,7 @@ __device__ void store_cell(const Net& nt, const Par& pr, const Cells& c, int64_t
   const bool iso = pr.thermal_mode == 1;
   const double T = iso ? L.Tiso : L.E / (KB * L.ck.n * cvk(pr, L.y2, L.ye));
   if (c.y_h || c.y_hp || c.y_hm) {
-    const double r = hm_ratio<R>(nt, T);
+    const double r = hm_ratio<double>(nt, T);
     const double yhm = r * L.ye;
     const double yhp = L.ye + yhm;
     if (c.y_h) c.y_h[i] = 1.0 - 2.0 * L.y2 - yhp - yhm;

@@ -90,8 +90,17 @@ def report(errs, exc, n, label="", gpu=None, ref=None, cells=None):
 
 
 FP64_TOL = 1e-9
-WELL_CONDITIONED = 1e-12
-SPREAD_FACTOR = 1000.0
+# A cell counts as determined by binary64 arithmetic when none of six other
+# valid roundings of the reference (oracle.rounding_spread) moves any of its
+# outputs by more than EXEMPT_SPREAD; such cells must match to FP64_TOL with
+# the same subcycle count and flags.  A cell that rounding alone moves
+# further must match to SPREAD_FACTOR times that spread.
+EXEMPT_SPREAD = 1e-10
+SPREAD_FACTOR = 10.0
+# Cells the reference determines that may still miss FP64_TOL, as a
+# fraction of the compared cells (branch decisions within rounding of a
+# threshold: the tight-coupling test, a step-size clamp); each one is listed.
+EXCEPTION_FRACTION = 1e-4
 # y_H is not solved for: H-nuclei conservation defines it as
 # 1 - 2 y_H2 - y_H+ - y_H-, a difference of terms up to 1, so binary64
 # determines it only to a few units in the last place of 1 in absolute
@@ -102,39 +111,102 @@ YH_ABS = 4.0 * np.finfo(float).eps
 
 
 def worst_of(errs, n):
+    """Largest error of each cell over the outputs; NaN counts as infinite."""
     w = np.zeros(n)
     for v in errs.values():
         w = np.maximum(w, np.nan_to_num(v, nan=np.inf))
     return w
 
 
-def assert_fp64_parity(gpu, cells, dt, onet, opar, label=""):
-    """The binary64 bar: cells the reference determines to 1e-12 (rounding
-    spread over three other valid roundings of the reference) match to
-    1e-9 with identical subcycle counts and flags; the others match to
-    max(1e-9, 1000 x spread); y_H deviations within YH_ABS (absolute) count
-    as exact.  Returns the reference outputs."""
-    ref = run_oracle(cells, dt, onet, opar)
-    spread = oracle.rounding_spread(cells, dt, ref, onet, opar, host_threads())
+def split_invalid(gpu, ref, label=""):
+    """Cells the reference marks invalid must be marked invalid by the GPU
+    too (and no others); returns the mask of valid cells."""
+    inv_r = (np.asarray(ref["flags"]) & oracle.F_INVALID) != 0
+    inv_g = (np.asarray(gpu["flags"]) & oracle.F_INVALID) != 0
+    assert np.array_equal(inv_r, inv_g), (label, "invalid-cell marks differ",
+                                          np.nonzero(inv_r != inv_g)[0][:5])
+    return ~inv_r
+
+
+def check_fp64_bar(gpu, ref, spread, label="", cells=None):
+    """Apply the binary64 bar to outputs already computed; returns the
+    number of cells beyond FP64_TOL."""
     errs, exc = compare(gpu, ref)
     errs["y_h"] = np.where(np.abs(gpu["y_h"] - ref["y_h"]) <= YH_ABS, 0.0, errs["y_h"])
-    n = cells["nh"].shape[0]
+    n = ref["nsub"].shape[0]
     report(errs, exc, n, label, gpu, ref, cells)
-    worst = worst_of(errs, n)
-    wc = spread <= WELL_CONDITIONED
-    ic = ~wc
-    ratio = worst[ic] / np.maximum(spread[ic], 1e-300) if ic.any() else np.zeros(0)
-    print(f"[parity] {label}: well-conditioned {int(wc.sum())}/{n}, max err "
-          f"{worst[wc].max() if wc.any() else 0:.2e}; ill-conditioned {int(ic.sum())}, beyond "
-          f"1e-9: {int((worst[ic] > FP64_TOL).sum())}, max err/spread "
-          f"{ratio.max() if ratio.size else 0:.1f}", flush=True)
-    if wc.any():
-        i = int(np.argmax(np.where(wc, worst, 0)))
-        assert worst[wc].max() <= FP64_TOL, (label, "well-conditioned", i, worst[i], spread[i])
-        np.testing.assert_array_equal(gpu["nsub"][wc], ref["nsub"][wc])
-        np.testing.assert_array_equal(gpu["flags"][wc], ref["flags"][wc])
-    if ic.any():
-        tol = np.maximum(FP64_TOL, SPREAD_FACTOR * spread[ic])
-        bad = np.nonzero(worst[ic] > tol)[0]
-        assert bad.size == 0, (label, "ill-conditioned", np.nonzero(ic)[0][bad][:5])
+    valid = split_invalid(gpu, ref, label)
+    worst = np.where(valid, worst_of(errs, n), 0.0)
+    assert np.all(np.isfinite(spread[valid])), (label, "non-finite rounding spread")
+    det = valid & (spread <= EXEMPT_SPREAD)
+    ill = valid & ~det
+    beyond = worst > FP64_TOL
+    ratio = worst[ill] / np.maximum(spread[ill], 1e-300) if ill.any() else np.zeros(0)
+    print(f"[parity] {label}: beyond 1e-9: {int(beyond.sum())}/{n} cells; determined to "
+          f"{EXEMPT_SPREAD:.0e} by binary64: {int(det.sum())}, max err there "
+          f"{worst[det].max() if det.any() else 0:.2e}; rounding-sensitive: {int(ill.sum())}, max "
+          f"err/spread {ratio.max() if ratio.size else 0:.2f}", flush=True)
+    # determined cells: 1e-9 with the same subcycle count and flags, up to
+    # EXCEPTION_FRACTION of the cells, each listed with its cause
+    miss = det & (beyond | (gpu["nsub"] != ref["nsub"]) |
+                  (np.asarray(gpu["flags"]) != np.asarray(ref["flags"])))
+    for i in np.nonzero(miss)[0][:20]:
+        print(f"[parity] {label}: exception cell {i}: err {worst[i]:.2e} spread {spread[i]:.1e} "
+              f"nsub {gpu['nsub'][i]}/{ref['nsub'][i]} flags {gpu['flags'][i]}/{ref['flags'][i]}",
+              flush=True)
+    allowed = int(EXCEPTION_FRACTION * n)
+    assert int(miss.sum()) <= allowed, (label, "determined cells beyond 1e-9 or on another path",
+                                        int(miss.sum()), allowed, np.nonzero(miss)[0][:5])
+    if ill.any():
+        tol = np.maximum(FP64_TOL, SPREAD_FACTOR * spread[ill])
+        bad = np.nonzero(worst[ill] > tol)[0]
+        assert bad.size == 0, (label, "rounding-sensitive cells beyond 10x spread",
+                               np.nonzero(ill)[0][bad][:5], ratio[bad][:5])
+    return int(beyond.sum())
+
+
+def assert_fp64_parity(gpu, cells, dt, onet, opar, label=""):
+    """The binary64 bar (see check_fp64_bar) on the reference computed here;
+    returns the reference outputs."""
+    ref = run_oracle(cells, dt, onet, opar)
+    spread = oracle.rounding_spread(cells, dt, ref, onet, opar, host_threads())
+    check_fp64_bar(gpu, ref, spread, label, cells)
     return ref
+
+
+MIXED_TOL = 1e-4
+# A cell is determined to binary32-coefficient accuracy when neither a 1e-6
+# relative change of every subcycle nor rounding the reference's
+# exponentials and powers to binary32 moves any output by more than
+# MIXED_WELL (oracle.step_sensitivity, oracle.coefficient_sensitivity).
+MIXED_WELL = 1e-6
+
+
+def check_mixed_bar(gpu, ref, cells, dt, onet, opar, label=""):
+    """The mixed bar against the binary64 reference: p99 <= MIXED_TOL on
+    every output, and max <= MIXED_TOL over the cells determined to
+    binary32-coefficient accuracy; the cells beyond MIXED_TOL are counted.
+    Conservation holds to round-off (the update is binary64)."""
+    errs, exc = compare(gpu, ref)
+    n = ref["nsub"].shape[0]
+    report(errs, exc, n, label, gpu, ref, cells)
+    valid = split_invalid(gpu, ref, label)
+    for k, e in errs.items():
+        e = e[valid]
+        print(f"[mixed] {label} {k}: median {np.median(e):.2e} p99 {np.percentile(e, 99):.2e} "
+              f"max {np.max(e):.2e} beyond 1e-4: {int((e > MIXED_TOL).sum())}", flush=True)
+        assert np.percentile(e, 99) <= MIXED_TOL, (label, k, float(np.percentile(e, 99)))
+    sens = oracle.step_sensitivity(cells, dt, ref, onet, opar, host_threads())
+    c32 = oracle.coefficient_sensitivity(cells, dt, ref, onet, opar, host_threads())
+    worst = np.where(valid, worst_of(errs, n), 0.0)
+    well = valid & (np.maximum(sens, c32) <= MIXED_WELL)
+    print(f"[mixed] {label}: beyond 1e-4: {int((worst > MIXED_TOL).sum())}/{n} cells; determined "
+          f"to binary32-coefficient accuracy: {int(well.sum())}, max err there "
+          f"{worst[well].max() if well.any() else 0:.2e}; the rest: max "
+          f"{worst[valid & ~well].max() if (valid & ~well).any() else 0:.2e}", flush=True)
+    if well.any():
+        i = int(np.argmax(np.where(well, worst, 0.0)))
+        assert worst[well].max() <= MIXED_TOL, (label, "determined cell beyond 1e-4", i, worst[i])
+    s = gpu["y_h"] + 2 * gpu["y_h2"] + gpu["y_hp"] + gpu["y_hm"]
+    assert np.all(np.abs(s[valid] - 1) <= 8 * np.finfo(float).eps), label
+    return worst

@@ -4,10 +4,12 @@ CPU reference's NR on the same seeded cells.
 NR stops each loop at a relative tolerance (1e-5, 1e-3 after 10 outer
 iterations), so where binary64 rounding flips a convergence decision the
 result moves by up to that tolerance.  Bar: cells the reference determines
-to 1e-12 (rounding spread over three other valid roundings of the
-reference NR) and that take the same substeps and outer iterations match
-to 1e-9 relative; every other cell matches to max(1e-9, 1000 x spread),
-or, where the iteration path differs, to the NR tolerance 1e-3.
+to 1e-10 (rounding spread over six other valid roundings of the reference
+NR) and that take the same substeps and outer iterations match to 1e-9
+relative; other cells on the same path match to max(1e-9, 10 x spread);
+where the iteration path differs (a convergence test decided within
+rounding of its tolerance), to the NR tolerance 1e-3.  The number of cells
+on another path is printed.
 """
 import numpy as np
 import pytest
@@ -52,14 +54,14 @@ def _check_nr(cells, dt, factor=1.0, par_over=None, label=""):
     report(errs, exc, n, label, gpu, ref, cells)
     worst = worst_of(errs, n)
     same_path = (gpu["nsub"] == ref["nsub"]) & (gpu["niter"] == ref["niter"])
-    wc = (spread <= 1e-12) & same_path
+    wc = (spread <= 1e-10) & same_path
     print(f"[nr] {label}: same path {int(same_path.sum())}/{n}, well-conditioned {int(wc.sum())}, "
           f"max err there {worst[wc].max() if wc.any() else 0:.2e}; others max {worst[~wc].max() if (~wc).any() else 0:.2e}; "
           f"NRFAIL gpu {int(((gpu['flags'] & 32) != 0).sum())} ref {int(((ref['flags'] & 32) != 0).sum())}",
           flush=True)
     if wc.any():
         assert worst[wc].max() <= 1e-9, (label, int(np.argmax(np.where(wc, worst, 0))))
-    tol = np.where(same_path, np.maximum(1e-9, 1000.0 * spread), np.maximum(NR_TOL, 1000.0 * spread))
+    tol = np.where(same_path, np.maximum(1e-9, 10.0 * spread), np.maximum(NR_TOL, 10.0 * spread))
     bad = np.nonzero(~wc & (worst > tol))[0]
     assert bad.size == 0, (label, bad[:5], worst[bad[:5]])
     return gpu, ref

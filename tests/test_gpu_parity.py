@@ -6,21 +6,24 @@ FP64 bar.  The subcycled LI map is ill-conditioned for part of the cells
 the operator-split fixed point): there, rounding alone moves the result by
 more than 1e-9, so no binary64 implementation with a different rounding
 can agree with the reference to 1e-9.  Each cell's rounding spread is
-measured from three other valid roundings of the reference itself
+measured from six other valid roundings of the reference itself
 (contracted multiply-adds with transcendentals nudged up by one ulp;
-transcendentals nudged down with powers formed as exp(y log x); the input
-energy moved by one ulp).  Then
-  - every cell the reference determines to 1e-12 (spread <= 1e-12) must
+transcendentals nudged down with powers formed as exp(y log x); quotients
+through a reciprocal moved one ulp up or down; the input energy moved by
+one ulp either way).  Then
+  - every cell the reference determines to 1e-10 (spread <= 1e-10) must
     match to 1e-9 relative on abundances (floor 1e-20) and on T_g, T_d,
-    with the same subcycle count and flags;
-  - every other cell must match to max(1e-9, 1000 x its spread), and their
-    number is reported.
-Mixed bar (binary32 rates, heating/cooling and Jacobian assembly): the
-assembled quantities agree with binary64 to ~5e-8 (median) and ~1e-6 (p99),
-but the same trajectories that are ill-conditioned in binary64 amplify
-those errors, so the bar is the median (<= 1e-4 on every output) and the
-full distribution (median, p99, max) is reported per species and
-temperature.
+    with the same subcycle count and flags; at most 1e-4 of the cells may
+    miss this (each is listed);
+  - every other cell must match to max(1e-9, 10 x its spread);
+  - the number of cells beyond 1e-9 is printed.
+Mixed bar (binary32 rate coefficients, heating/cooling and Jacobian
+assembly; net sources summed, dust terms and every solve in binary64):
+1e-4 relative against the binary64 reference on every output at p99, and
+at the maximum over the cells whose reference trajectory is insensitive to
+its step sizes (a 1e-6 relative change of every subcycle moves no output
+by more than 1e-6); the full distribution (median, p99, max) is printed
+per species and temperature, and the remaining cells beyond 1e-4 counted.
 """
 import math
 
@@ -29,14 +32,11 @@ import pytest
 
 import oracle
 from conftest import cell_dict
-from parity_util import (FP64_TOL, SPREAD_FACTOR, WELL_CONDITIONED, assert_fp64_parity, compare,
-                         host_threads, oracle_net_params, report, run_gpu, run_oracle, worst_of)
+from parity_util import (assert_fp64_parity, check_fp64_bar, check_mixed_bar, host_threads,
+                         oracle_net_params, run_gpu, run_oracle)
 from paper_2604_21438_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
-
-MIXED_TOL = 1e-4
-
 
 def _sfc():
     import paper_2604_21438_amd as sfc
@@ -102,7 +102,7 @@ def test_mixed_full_temperature_range():
     """The mixed path on the same 1 K - 1e8 K cells: binary32 assembly
     stays finite (powers of T up to T^3.8 ~ 1e30 and the Boltzmann factors
     are inside or flushed below the binary32 range), conservation holds in
-    the binary64 update, and the median bar holds for every output."""
+    the binary64 update, and the mixed bar holds."""
     sfc = _sfc()
     cells = W.uniform_population(2048, seed_offset=31)
     rng = np.random.default_rng(31)
@@ -117,14 +117,7 @@ def test_mixed_full_temperature_range():
         assert np.all(np.isfinite(gpu[k])), k
     onet, opar = oracle_net_params(net, par, 1.0)
     ref = run_oracle(cells, 3.15576e10, onet, opar)
-    errs, exc = compare(gpu, ref)
-    report(errs, exc, 2048, "mixed 1 K - 1e8 K", gpu, ref, cells)
-    for k, e in errs.items():
-        print(f"[mixed 1 K - 1e8 K] {k}: median {np.median(e):.2e} p99 {np.percentile(e, 99):.2e} "
-              f"max {np.max(e):.2e}", flush=True)
-        assert np.median(e) <= MIXED_TOL, (k, float(np.median(e)))
-    s = gpu["y_h"] + 2 * gpu["y_h2"] + gpu["y_hp"] + gpu["y_hm"]
-    assert np.all(np.abs(s - 1) <= 8 * np.finfo(float).eps)
+    check_mixed_bar(gpu, ref, cells, 3.15576e10, onet, opar, "mixed 1 K - 1e8 K")
 
 
 def test_fp64_evolve_ir():
@@ -216,7 +209,8 @@ def test_photoionisation_equilibrium_on_gpu():
 
 
 def test_mixed_small_cells():
-    """Binary32 assembly / binary64 solve against the binary64 reference."""
+    """Binary32 assembly / binary64 sums, dust terms and solves against the
+    binary64 reference on the 4096-cell population."""
     sfc = _sfc()
     cells, dt = W.small_cells()
     net = sfc.default_network()
@@ -224,25 +218,23 @@ def test_mixed_small_cells():
     gpu = run_gpu(cells, dt, sfc.MIXED, 1.0, net, par, label="mixed 4096")
     onet, opar = oracle_net_params(net, par, 1.0)
     ref = run_oracle(cells, dt, onet, opar)
-    errs, exc = compare(gpu, ref)
-    n = cells["nh"].shape[0]
-    report(errs, exc, n, "mixed 4096 cells", gpu, ref, cells)
-    for k, e in errs.items():
-        print(f"[mixed] {k}: median {np.median(e):.2e} p90 {np.percentile(e, 90):.2e} "
-              f"p99 {np.percentile(e, 99):.2e} max {np.max(e):.2e}", flush=True)
-        assert np.median(e) <= MIXED_TOL, (k, float(np.median(e)))
-    # error by how well binary64 rounding determines the cell (reported)
-    spread = oracle.rounding_spread(cells, dt, ref, onet, opar, host_threads())
-    worst = worst_of(errs, n)
-    for lim in (1e-15, 1e-14, 1e-13, 1e-12, np.inf):
-        m = spread <= lim
-        if m.any():
-            print(f"[mixed] spread <= {lim:.0e}: {int(m.sum())} cells, worst-output error "
-                  f"median {np.median(worst[m]):.2e} p99 {np.percentile(worst[m], 99):.2e} "
-                  f"max {worst[m].max():.2e}", flush=True)
-    # conservation holds to round-off in the binary64 update
-    s = gpu["y_h"] + 2 * gpu["y_h2"] + gpu["y_hp"] + gpu["y_hm"]
-    assert np.all(np.abs(s - 1) <= 8 * np.finfo(float).eps)
+    check_mixed_bar(gpu, ref, cells, dt, onet, opar, "mixed 4096 cells")
+
+
+def test_mixed_grid128_and_hii():
+    """The mixed bar on the 128^3 population (a seeded subsample, dust
+    factor 1) and on the H II region stand-in."""
+    sfc = _sfc()
+    cells, dt = W.grid128(n=200_000)
+    sub, _ = W.subsample(cells, 3000, seed=11)
+    hii, dth = W.hii_region(2048)
+    for c, d, label in ((sub, dt, "mixed grid128 subsample"), (hii, dth, "mixed H II stand-in")):
+        net = sfc.default_network()
+        par = sfc.default_params()
+        gpu = run_gpu(c, d, sfc.MIXED, 1.0, net, par, label=label)
+        onet, opar = oracle_net_params(net, par, 1.0)
+        ref = run_oracle(c, d, onet, opar)
+        check_mixed_bar(gpu, ref, c, d, onet, opar, label)
 
 
 def test_fp64_full_grid128_sampled():
@@ -261,12 +253,7 @@ def test_fp64_full_grid128_sampled():
     ref = run_oracle(sub, dt, onet, opar)
     spread = oracle.rounding_spread(sub, dt, ref, onet, opar, host_threads())
     g = {k: v[idx] for k, v in gpu.items()}
-    errs, exc = compare(g, ref)
-    report(errs, exc, len(idx), "grid128 full, sampled", g, ref, sub)
-    worst = worst_of(errs, len(idx))
-    tol = np.where(spread <= WELL_CONDITIONED, FP64_TOL,
-                   np.maximum(FP64_TOL, SPREAD_FACTOR * spread))
-    assert np.all(worst <= tol), np.nonzero(worst > tol)[0]
+    check_fp64_bar(g, ref, spread, "grid128 full, sampled", sub)
 
 
 BITWISE_KEYS = ("y_h2", "y_e", "eint", "tdust", "y_h", "y_hp", "y_hm", "tgas", "nsub", "niter",
@@ -397,26 +384,24 @@ def test_plain_step_graph_replay():
 
 def test_grid256_population():
     """256^3 log-normal density with an n^-1.5 tail, 8 point sources, dust
-    factor 100: binary64 parity on a seeded subsample, then the whole
-    16.7M-cell population in one mixed launch, every cell processed and 200
-    sampled cells compared with the binary64 reference (median bar; the
-    distribution is printed)."""
+    factor 100: binary64 parity on a seeded subsample, the mixed bar on
+    another, then the whole 16.7M-cell population in one mixed launch,
+    every cell processed and 1000 sampled cells held to the mixed bar."""
     sfc = _sfc()
     cells, dt = W.grid256()
     sub, _ = W.subsample(cells, 3000, seed=13)
     _check_fp64(sub, dt, 100.0, label="grid256 subsample factor 100")
     net = sfc.default_network()
     par = sfc.default_params()
+    onet, opar = oracle_net_params(net, par, 100.0)
+    g = run_gpu(sub, dt, sfc.MIXED, 100.0, net, par, label="grid256 subsample mixed")
+    check_mixed_bar(g, run_oracle(sub, dt, onet, opar), sub, dt, onet, opar,
+                    "grid256 subsample mixed")
     gpu = run_gpu(cells, dt, sfc.MIXED, 100.0, net, par, label="grid256 full mixed")
     assert np.all(gpu["nsub"] > 0)
     rng = np.random.default_rng(7)
-    idx = np.sort(rng.choice(cells["nh"].shape[0], 200, replace=False))
+    idx = np.sort(rng.choice(cells["nh"].shape[0], 1000, replace=False))
     s2 = {k: np.ascontiguousarray(v[idx]) for k, v in cells.items()}
-    onet, opar = oracle_net_params(net, par, 100.0)
     ref = run_oracle(s2, dt, onet, opar)
-    errs, exc = compare({k: v[idx] for k, v in gpu.items()}, ref)
-    report(errs, exc, len(idx), "grid256 full mixed, sampled")
-    for k, e in errs.items():
-        print(f"[mixed grid256] {k}: median {np.median(e):.2e} p99 {np.percentile(e, 99):.2e} "
-              f"max {np.max(e):.2e}", flush=True)
-        assert np.median(e) <= MIXED_TOL, (k, float(np.median(e)))
+    check_mixed_bar({k: v[idx] for k, v in gpu.items()}, ref, s2, dt, onet, opar,
+                    "grid256 full mixed, sampled")
