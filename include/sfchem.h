@@ -34,7 +34,7 @@ extern "C" {
 
 /* Version of sfc_network and sfc_params (both checked through
  * sfc_network.abi_version). */
-#define SFC_ABI_VERSION 3u
+#define SFC_ABI_VERSION 4u
 
 enum {
   SFC_OK = 0,
@@ -207,16 +207,44 @@ int sfc_chem_step_nr(sfc_ctx* ctx, const sfc_cells* cells, double dt_seconds, vo
 
 /* ---- served form: continuous batching of AMR blocks ---- */
 
-/* One request: a set of cells (typically whole 8^3 blocks) with its own dt.
- * The buffers are caller-owned device memory and must stay valid until the
- * request completes (sfc_chem_poll returns SFC_OK); results are written
- * back into them. */
+/* One request: a set of cells (typically whole 8^3 blocks) with its own dt
+ * (the AMR substep of its level, Eqs. timestep and timestep2 of the paper).
+ *
+ * Without a block key (block_key == 0) the request's cells are copied from
+ * the caller's buffers into the library's arena when it is admitted, and
+ * its results are copied back into the same buffers when it completes; the
+ * buffers must stay valid until sfc_chem_poll returns SFC_OK.
+ *
+ * With a block key the block's state stays resident in the arena between
+ * requests, as AMR substeps of one block follow each other:
+ *   - a request without SFC_REQ_RESUME uploads `cells` into the key's range
+ *     (the first substep, or a restart); the key keeps its cell count;
+ *   - a request with SFC_REQ_RESUME continues from the state the key's
+ *     previous request left (and its inputs n_H, photon densities, Z): no
+ *     copy-in, `cells` is not read (cells.n may be 0 or the key's count);
+ *   - results stay in the arena: sfc_chem_fetch copies them out, and
+ *     SFC_REQ_WRITEBACK also copies them into `cells` at completion;
+ *   - the key's requests run one after the other in submission order; a
+ *     request may be submitted before its predecessor is done;
+ *   - the key holds its arena range until sfc_chem_release.
+ * hip_stream, if not NULL, is the stream that produced the input buffers:
+ * the library's copy-in waits for the work queued on it before the submit
+ * call (otherwise the caller must have completed that work first). */
+enum {
+  SFC_REQ_RESUME = 1u << 0,    /* continue from the block key's resident state */
+  SFC_REQ_WRITEBACK = 1u << 1  /* keyed request: also copy results into cells */
+};
+
 typedef struct {
   sfc_cells cells;
   double dt_seconds;
   int32_t level;       /* AMR level: claim priority (see submit)  */
   int32_t precision;   /* SFC_FP64 or SFC_MIXED                   */
   uint64_t tag;        /* caller's tag, returned in sfc_result    */
+  uint64_t block_key;  /* resident block (0: none)                */
+  uint32_t flags;      /* SFC_REQ_* bits                          */
+  uint32_t reserved;   /* must be 0                               */
+  void* hip_stream;    /* producer stream of the inputs, or NULL  */
 } sfc_request;
 
 typedef struct {
@@ -229,23 +257,47 @@ typedef struct {
 
 /* Queue a request (non-blocking; the descriptor is copied).  The library's
  * scheduler thread admits requests in arrival order while their state fits
- * the HBM budget, uploads them into its arena and drains all admitted work
- * with a persistent kernel replayed as a HIP graph; results are copied back
- * when a request's last block is done.  Idle lanes take the cells of the
- * oldest admitted request with cells left.  The waves holding cells of a
- * finer AMR level issue first on their SIMD (level >= 5, 4, 3 above the
- * rest): a level-L block is advanced 2^L times per coarse step, so the
- * finest level's substeps form the longest chain of dependent requests,
- * each as long as its slowest cell.  Results do not depend on either
- * order.  Environment variables read when the context is created:
+ * the HBM budget (a keyed request whose block already holds its range needs
+ * no room and is not held back by others waiting for room), stages them
+ * into its arena and drains all admitted work with a persistent kernel
+ * replayed as a HIP graph.  Idle lanes take the cells of the oldest
+ * admitted request with cells left.  The waves holding cells of a finer
+ * AMR level issue first on their SIMD (level >= 5, 4, 3 above the rest): a
+ * level-L block is advanced 2^L times per coarse step, so the finest
+ * level's substeps form the longest chain of dependent requests, each as
+ * long as its slowest cell.  Results do not depend on either order.
+ * Environment variables read when the context is created:
  * SFC_SERVE_LEVEL_CLAIMS=1 hands out the cells of the highest level first
  * (levels above 7 count as 7, negative ones as 0; a steady stream of fine
  * requests then delays coarse ones without bound), SFC_SERVE_LEVEL_PRIO=0
- * turns the issue priority off.  Up to 16384 requests per level class and
- * precision may be in flight; admission waits beyond that.
- * Errors: SFC_E_INVAL, SFC_E_BUDGET (larger than the whole budget),
- * SFC_E_STATE (served form disabled). */
+ * turns the issue priority off, SFC_SERVE_RING (a power of two, 2..16384,
+ * default 16384) sets how many requests per level class and precision may
+ * be in flight; admission waits beyond that.
+ * Errors: SFC_E_INVAL (bad buffers, dt, precision or flags; 2^31 cells or
+ * more; a block key resubmitted with another cell count; SFC_REQ_RESUME
+ * without a key), SFC_E_STATE (served form disabled; SFC_REQ_RESUME on a key
+ * with no resident state, or on a key being released), SFC_E_BUDGET (larger
+ * than the whole budget). */
 int sfc_chem_submit(sfc_ctx* ctx, const sfc_request* req, uint64_t* ticket);
+
+/* Copy the results of a completed keyed request (ticket) from the arena
+ * into dst (device buffers of the key's cell count; any array may be NULL
+ * and is then skipped: y_h2, y_e, eint, tdust, eir, y_h, y_hp, y_hm, tgas,
+ * nsub, niter, flags) on hip_stream (NULL = default stream).  Asynchronous:
+ * the copy is queued on that stream, and the key's next request does not
+ * start before it has run.  Valid while the ticket is its key's latest
+ * request and the key is not released (also after sfc_chem_poll).
+ * Errors: SFC_E_PENDING (not done yet), SFC_E_STATE (a later request of the
+ * key was submitted, the key was released, the request failed, or the
+ * ticket has no block key), SFC_E_INVAL (bad arguments or cell count),
+ * SFC_E_DEVICE. */
+int sfc_chem_fetch(sfc_ctx* ctx, uint64_t ticket, const sfc_cells* dst, void* hip_stream);
+
+/* Give a block key's arena range back, once the key's requests are done
+ * (immediately if none is in flight).  Its results can no longer be
+ * fetched.  Errors: SFC_E_INVAL (unknown key), SFC_E_STATE (served form
+ * disabled). */
+int sfc_chem_release(sfc_ctx* ctx, uint64_t block_key);
 
 /* Non-blocking completion check: SFC_OK and *out filled when done (the
  * ticket is then released), SFC_E_PENDING otherwise, SFC_E_INVAL for an

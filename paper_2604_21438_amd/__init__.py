@@ -23,7 +23,8 @@ THERMAL_EVOLVE, THERMAL_ISOTHERMAL = 0, 1
 DUST_EVOLVE, DUST_FROZEN = 0, 1
 F_CAP, F_TIGHT, F_NOCONV, F_INVALID, F_FLOOR, F_NRFAIL = 1, 2, 4, 8, 16, 32
 OK, E_INVAL, E_NOMEM, E_BUDGET, E_DEVICE, E_PENDING, E_VERSION, E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
-ABI_VERSION = 3
+ABI_VERSION = 4
+REQ_RESUME, REQ_WRITEBACK = 1, 2
 NREAC, NPROC, NLINE = 12, 14, 5
 
 _d = C.c_double
@@ -64,7 +65,8 @@ class SfcCells(C.Structure):
 
 class SfcRequest(C.Structure):
     _fields_ = [("cells", SfcCells), ("dt_seconds", _d), ("level", C.c_int32),
-                ("precision", C.c_int32), ("tag", C.c_uint64)]
+                ("precision", C.c_int32), ("tag", C.c_uint64), ("block_key", C.c_uint64),
+                ("flags", C.c_uint32), ("reserved", C.c_uint32), ("hip_stream", C.c_void_p)]
 
 
 class SfcResult(C.Structure):
@@ -73,8 +75,9 @@ class SfcResult(C.Structure):
 
 
 EXPORTS = ("sfc_network_default", "sfc_params_default", "sfc_chem_init", "sfc_chem_step",
-           "sfc_chem_step_nr", "sfc_chem_submit", "sfc_chem_poll", "sfc_chem_drain", "sfc_chem_destroy",
-           "sfc_strerror", "sfc_last_error", "sfc_now")
+           "sfc_chem_step_nr", "sfc_chem_submit", "sfc_chem_poll", "sfc_chem_fetch",
+           "sfc_chem_release", "sfc_chem_drain", "sfc_chem_destroy", "sfc_strerror",
+           "sfc_last_error", "sfc_now")
 
 _LIB = None
 
@@ -101,6 +104,8 @@ def lib():
         L.sfc_chem_step_nr.argtypes = [C.c_void_p, P(SfcCells), _d, C.c_void_p]
         L.sfc_chem_submit.argtypes = [C.c_void_p, P(SfcRequest), P(C.c_uint64)]
         L.sfc_chem_poll.argtypes = [C.c_void_p, C.c_uint64, P(SfcResult)]
+        L.sfc_chem_fetch.argtypes = [C.c_void_p, C.c_uint64, P(SfcCells), C.c_void_p]
+        L.sfc_chem_release.argtypes = [C.c_void_p, C.c_uint64]
         L.sfc_chem_drain.argtypes = [C.c_void_p]
         L.sfc_chem_destroy.argtypes = [C.c_void_p]
         L.sfc_strerror.argtypes = [C.c_int]
@@ -109,8 +114,8 @@ def lib():
         L.sfc_last_error.restype = C.c_char_p
         L.sfc_now.restype = _d
         for name in ("sfc_chem_init", "sfc_chem_step", "sfc_chem_step_nr", "sfc_chem_submit",
-                     "sfc_chem_poll",
-                     "sfc_chem_drain", "sfc_chem_destroy"):
+                     "sfc_chem_poll", "sfc_chem_fetch", "sfc_chem_release", "sfc_chem_drain",
+                     "sfc_chem_destroy"):
             getattr(L, name).restype = C.c_int
         _LIB = L
     return _LIB
@@ -176,7 +181,7 @@ def make_cells(t: dict) -> SfcCells:
     """SfcCells view of a dict of device tensors (missing keys -> NULL)."""
     import torch
     n = None
-    for k in STATE + INPUTS:
+    for k in STATE + INPUTS + OUT_F + OUT_I:
         if k in t and t[k] is not None:
             n = t[k].shape[0]
             break
@@ -246,26 +251,45 @@ class Context:
         sp = C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
         self._check(lib().sfc_chem_step_nr(self._h, C.byref(c), float(dt), sp), "sfc_chem_step_nr")
 
-    def submit(self, cells: dict, dt: float, precision: int = MIXED, level: int = 0,
-               tag: int = 0, sync: bool = True) -> int:
-        """Queue a request; the tensors are updated in place once poll()
-        reports it done.  The library reads them on its own stream, so by
-        default torch's current stream is synchronised first.  `level` is
-        the AMR level: waves holding cells of finer levels issue first, and
-        with SFC_SERVE_LEVEL_CLAIMS=1 (read when the context is created)
-        finer levels are also handed out first."""
+    def _stream(self, stream):
         import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+    def submit(self, cells, dt: float, precision: int = MIXED, level: int = 0, tag: int = 0,
+               sync: bool = True, block_key: int = 0, resume: bool = False,
+               writeback: bool = False, stream=None) -> int:
+        """Queue a request; without a block key the tensors are updated in
+        place once poll() reports it done.  The library reads the inputs on
+        its own stream: by default torch's current stream is synchronised
+        first; with sync=False the library instead waits (on the device) for
+        the work queued on `stream` (default: torch's current stream).
+        `level` is the AMR level: waves holding cells of finer levels issue
+        first, and with SFC_SERVE_LEVEL_CLAIMS=1 (read when the context is
+        created) finer levels are also handed out first.  With a block key
+        the block's state stays resident between requests: `resume`
+        continues from it (cells may be None), results are read with
+        fetch(), and `writeback` also copies them into `cells`."""
+        import torch
+        r = SfcRequest()
+        if cells is not None:
+            r.cells = make_cells(cells)
         if sync:
             torch.cuda.current_stream(self.device).synchronize()
-        r = SfcRequest()
-        r.cells = make_cells(cells)
+            r.hip_stream = None
+        else:
+            r.hip_stream = self._stream(stream)
         r.dt_seconds = float(dt)
         r.level = int(level)
         r.precision = int(precision)
         r.tag = int(tag)
+        r.block_key = int(block_key)
+        r.flags = (REQ_RESUME if resume else 0) | (REQ_WRITEBACK if writeback else 0)
         t = C.c_uint64()
         self._check(lib().sfc_chem_submit(self._h, C.byref(r), C.byref(t)), "sfc_chem_submit")
-        self._keep[t.value] = cells  # buffers must outlive the request
+        if cells is not None:
+            self._keep[t.value] = cells  # buffers must outlive the request
         return t.value
 
     def poll(self, ticket: int):
@@ -278,6 +302,21 @@ class Context:
         self._keep.pop(int(ticket), None)
         return dict(status=res.status, level=res.level, tag=res.tag, cells=res.cells,
                     t_submit=res.t_submit, t_admit=res.t_admit, t_done=res.t_done)
+
+    def fetch(self, ticket: int, cells: dict, stream=None) -> bool:
+        """Copy the results of a completed keyed request into `cells`
+        (device tensors; missing keys are skipped), queued on `stream`
+        (default: torch's current stream).  False while it is pending."""
+        c = make_cells(cells)
+        rc = lib().sfc_chem_fetch(self._h, int(ticket), C.byref(c), self._stream(stream))
+        if rc == E_PENDING:
+            return False
+        self._check(rc, "sfc_chem_fetch")
+        return True
+
+    def release(self, block_key: int) -> None:
+        """Give a block key's arena range back."""
+        self._check(lib().sfc_chem_release(self._h, int(block_key)), "sfc_chem_release")
 
     def drain(self) -> None:
         self._check(lib().sfc_chem_drain(self._h), "sfc_chem_drain")

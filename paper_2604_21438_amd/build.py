@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsfchem.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["sfk_li.hip", "sfk_serve.hip", "sfserve.cpp", "sfchem.cpp"]
+SOURCES = ["sfk_li.hip", "sfk_serve.hip", "sfsched.cpp", "sfserve.cpp", "sfchem.cpp"]
 # Extra device flags per source.  The LI kernels run one cell per lane for
 # thousands of loop iterations; machine LICM hoists every loop-invariant
 # binary64 constant (and products of them) out of that loop into registers,

@@ -475,15 +475,20 @@ int sfc_chem_step_nr(sfc_ctx* ctx, const sfc_cells* cells, double dt, void* hip_
 int sfc_chem_submit(sfc_ctx* ctx, const sfc_request* req, uint64_t* ticket) {
   if (!ctx || !req || !ticket) return SFC_E_INVAL;
   if (!ctx->server) return fail(ctx, SFC_E_STATE, "served form disabled (budget 0)");
-  if (!cells_ok(ctx->par, &req->cells) || req->cells.n <= 0)
+  const uint32_t known = SFC_REQ_RESUME | SFC_REQ_WRITEBACK;
+  if ((req->flags & ~known) != 0 || req->reserved != 0)
+    return fail(ctx, SFC_E_INVAL, "sfc_chem_submit: unknown flags");
+  const bool resume = (req->flags & SFC_REQ_RESUME) != 0;
+  if (req->cells.n < 0 || (!resume && (!cells_ok(ctx->par, &req->cells) || req->cells.n == 0)))
     return fail(ctx, SFC_E_INVAL, "sfc_chem_submit: bad cell buffers");
   if (!(req->dt_seconds > 0.0) || !std::isfinite(req->dt_seconds))
     return fail(ctx, SFC_E_INVAL, "sfc_chem_submit: dt must be positive and finite");
   if (req->precision != SFC_FP64 && req->precision != SFC_MIXED)
     return fail(ctx, SFC_E_INVAL, "sfc_chem_submit: unknown precision");
+  DeviceGuard g(ctx->device);
   std::string err;
   const int rc = sfserve::submit(ctx->server, *req, ticket, &err);
-  if (rc != SFC_OK) return fail(ctx, rc, err);
+  if (rc != SFC_OK) return fail(ctx, rc, "sfc_chem_submit: " + err);
   return SFC_OK;
 }
 
@@ -491,6 +496,25 @@ int sfc_chem_poll(sfc_ctx* ctx, uint64_t ticket, sfc_result* out) {
   if (!ctx || !out) return SFC_E_INVAL;
   if (!ctx->server) return fail(ctx, SFC_E_STATE, "served form disabled (budget 0)");
   return sfserve::poll(ctx->server, ticket, out);
+}
+
+int sfc_chem_fetch(sfc_ctx* ctx, uint64_t ticket, const sfc_cells* dst, void* hip_stream) {
+  if (!ctx || !dst || dst->n <= 0) return SFC_E_INVAL;
+  if (!ctx->server) return fail(ctx, SFC_E_STATE, "served form disabled (budget 0)");
+  DeviceGuard g(ctx->device);
+  std::string err;
+  const int rc = sfserve::fetch(ctx->server, ticket, *dst, hip_stream, &err);
+  if (rc != SFC_OK && rc != SFC_E_PENDING) return fail(ctx, rc, "sfc_chem_fetch: " + err);
+  return rc;
+}
+
+int sfc_chem_release(sfc_ctx* ctx, uint64_t block_key) {
+  if (!ctx) return SFC_E_INVAL;
+  if (!ctx->server) return fail(ctx, SFC_E_STATE, "served form disabled (budget 0)");
+  std::string err;
+  const int rc = sfserve::release(ctx->server, block_key, &err);
+  if (rc != SFC_OK) return fail(ctx, rc, "sfc_chem_release: " + err);
+  return SFC_OK;
 }
 
 int sfc_chem_drain(sfc_ctx* ctx) {

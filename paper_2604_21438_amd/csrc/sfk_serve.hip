@@ -9,13 +9,13 @@ namespace sfk {
 namespace {
 
 // ------------------------------------------------------------------ served
-__device__ inline uint64_t sys_load(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+__device__ inline uint64_t agent_load(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// The ring entry a wave last claimed from; every lane holds the same copy.
+// The slot descriptor a wave last claimed from; every lane holds the same copy.
 struct WaveCache {
-  uint64_t k = ~0ull;  // request sequence number of the cached entry
+  uint64_t k = ~0ull;  // request sequence number of the cached descriptor
   int cls = -1;        // its class
   uint64_t n = 0, off = 0, lvl = 0;
   double dt = 0.0;
@@ -34,17 +34,44 @@ struct Claim {
   int take;
 };
 
+// Read the descriptor of ring slot m into c if it belongs to the request
+// whose sequence number has the low 32 bits `tag` (seqlock: the arm kernel
+// writes ~0, the fields, then the sequence number, with release fences
+// between).  Returns false if the slot holds another request, or is being
+// rewritten for one.
+__device__ inline bool read_meta(const SlotMeta* m, uint32_t tag, int cls, WaveCache& c) {
+  const uint64_t s1 = agent_load(&m->seq);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  const uint64_t n = agent_load(&m->n);
+  const uint64_t off = agent_load(&m->off);
+  const uint64_t lvl = agent_load(&m->level);
+  const uint64_t dtb = agent_load(reinterpret_cast<const uint64_t*>(&m->dt));
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  const uint64_t s2 = agent_load(&m->seq);
+  if (s1 != s2 || s1 == ~0ull || uint32_t(s1) != tag) return false;
+  c.k = s1;
+  c.cls = cls;
+  c.n = n;
+  c.off = off;
+  c.lvl = lvl;
+  c.dt = __longlong_as_double((long long)dtb);
+  return true;
+}
+
 // Claim up to `want` cells for one wave.  Wave-uniform call: every lane
 // takes part and gets the same result.  Lane l < kClasses inspects class l,
 // so one round of loads covers every class, and the wave takes cells of the
 // oldest request of the highest class with unclaimed cells.  The host's
 // published count of a class is read only when the class looks exhausted
-// and a copy-in was launched since the largest count read so far, which is
+// and a request was armed since the largest count read so far, which is
 // kept in device memory for every wave.  The cells come from one atomicAdd
-// on the request's slot counter, so concurrent waves never retry; a request
+// on the slot's claim word, so concurrent waves never retry; a request
 // found exhausted moves its class head on (compare-and-swap; a failure
-// means another wave already did).  Lane kClasses reads the newest launch
-// generation of this precision: take = -1 when it is newer than `gen`.
+// means another wave already did).  If the claim word carries another
+// request's tag, the slot was armed again, so the head's request is done:
+// the head moves on and the cells handed out are the newer request's.
+// Lane kClasses reads the newest launch generation of this precision:
+// take = -1 when it is newer than `gen`.
 __device__ Claim claim_cells(const ServedArgs& a, int want, WaveCache& c, int lane,
                              uint64_t gen) {
   Claim r{0, 0, 0, 0.0, 0};
@@ -70,36 +97,34 @@ __device__ Claim claim_cells(const ServedArgs& a, int want, WaveCache& c, int la
     if (avail == 0ull) return r;
     const int cls = 63 - __clzll((long long)avail);
     const uint64_t kc = __shfl(k, cls);
-    const size_t slot = size_t(cls) * kRing + size_t(kc % kRing);
+    const size_t slot = size_t(cls) * a.ring + size_t(kc & (a.ring - 1));
     uint64_t first = 0;
     int take = 0;
     if (lane == 0) {
-      bool ok = true;
-      if (kc != c.k || cls != c.cls) {
-        const RingEntry* e = a.ring + slot;
-        if (__hip_atomic_load(&e->seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) != kc) {
-          ok = false;  // not visible yet, or the head moved on: look again
-        } else {
-          c.n = sys_load(&e->n);
-          c.off = sys_load(&e->arena_off);
-          c.lvl = sys_load(&e->level);
-          c.dt = __longlong_as_double((long long)sys_load(reinterpret_cast<const uint64_t*>(&e->dt)));
-          c.k = kc;
-          c.cls = cls;
-        }
+      const unsigned long long w = __hip_atomic_fetch_add(
+          a.claimed + slot, (unsigned long long)want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const uint32_t tag = uint32_t(w >> 32);
+      const uint64_t o = w & 0xffffffffull;
+      bool have;
+      if (tag == uint32_t(kc)) {
+        have = (c.k == kc && c.cls == cls) || read_meta(a.meta + slot, tag, cls, c);
+      } else {
+        // the slot holds a newer request of this class: kc is done
+        unsigned long long expect = kc;
+        __hip_atomic_compare_exchange_strong(a.head + cls, &expect, kc + 1, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        have = (uint32_t(c.k) == tag && c.cls == cls && c.k != ~0ull) ||
+               read_meta(a.meta + slot, tag, cls, c);
       }
-      if (ok) {
-        const uint32_t o = __hip_atomic_fetch_add(a.claimed + slot, uint32_t(want),
-                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (uint64_t(o) < c.n) {
-          const uint64_t left = c.n - o;
-          first = o;
-          take = int(left < uint64_t(want) ? left : uint64_t(want));
-        } else {
-          unsigned long long expect = kc;
-          __hip_atomic_compare_exchange_strong(a.head + cls, &expect, kc + 1, __ATOMIC_RELAXED,
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+      if (have && o < c.n) {
+        const uint64_t left = c.n - o;
+        first = o;
+        take = int(left < uint64_t(want) ? left : uint64_t(want));
+      } else if (tag == uint32_t(kc)) {
+        unsigned long long expect = kc;
+        __hip_atomic_compare_exchange_strong(a.head + cls, &expect, kc + 1, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
     c.k = __shfl(c.k, 0);
@@ -110,7 +135,7 @@ __device__ Claim claim_cells(const ServedArgs& a, int want, WaveCache& c, int la
     c.dt = __shfl(c.dt, 0);
     take = __shfl(take, 0);
     if (take > 0) {
-      r.tk = (uint64_t(cls) << kClassShift) | (c.lvl << kLevelShift) | (kc & kSeqMask);
+      r.tk = (uint64_t(cls) << kClassShift) | (c.lvl << kLevelShift) | (c.k & kSeqMask);
       r.first = __shfl(first, 0);
       r.off = c.off;
       r.dt = c.dt;
@@ -131,7 +156,7 @@ __device__ inline void flush_done(const ServedArgs& a, uint64_t& pend) {
   if (pend) {
     const uint64_t tk = pend - 1;
     const uint64_t seq = tk & kSeqMask;
-    const size_t slot = size_t(tk >> kClassShift) * kRing + size_t(seq % kRing);
+    const size_t slot = size_t(tk >> kClassShift) * a.ring + size_t(seq & (a.ring - 1));
     const int left = __hip_atomic_fetch_add(a.remaining + slot, -1, __ATOMIC_RELAXED,
                                             __HIP_MEMORY_SCOPE_AGENT);
     if (left == 1) {
@@ -256,11 +281,6 @@ __global__ __launch_bounds__(kBlock) void served_drain_kernel(ServedArgs) {
 
 __global__ __launch_bounds__(256) void copy_in_kernel(CopyArgs a) {
   const int64_t n = a.user.n;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (a.remaining_slot) *a.remaining_slot = int32_t(n);
-    if (a.claimed_slot) *a.claimed_slot = 0u;
-    if (a.staged) __hip_atomic_fetch_add(a.staged, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x) {
     const int64_t j = a.off + i;
@@ -276,16 +296,18 @@ __global__ __launch_bounds__(256) void copy_in_kernel(CopyArgs a) {
   }
 }
 
+// Results of a request (or a resident block) into the caller's buffers;
+// arrays the caller passes as NULL are skipped.
 __global__ __launch_bounds__(256) void copy_out_kernel(CopyArgs a) {
   const int64_t n = a.user.n;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x) {
     const int64_t j = a.off + i;
-    a.user.y_h2[i] = a.arena.y_h2[j];
-    a.user.y_e[i] = a.arena.y_e[j];
-    a.user.eint[i] = a.arena.eint[j];
-    a.user.tdust[i] = a.arena.tdust[j];
-    if (a.ir_evolve) a.user.eir[i] = a.arena.eir[j];
+    if (a.user.y_h2) a.user.y_h2[i] = a.arena.y_h2[j];
+    if (a.user.y_e) a.user.y_e[i] = a.arena.y_e[j];
+    if (a.user.eint) a.user.eint[i] = a.arena.eint[j];
+    if (a.user.tdust) a.user.tdust[i] = a.arena.tdust[j];
+    if (a.ir_evolve && a.user.eir) a.user.eir[i] = a.arena.eir[j];
     if (a.user.y_h) a.user.y_h[i] = a.arena.y_h[j];
     if (a.user.y_hp) a.user.y_hp[i] = a.arena.y_hp[j];
     if (a.user.y_hm) a.user.y_hm[i] = a.arena.y_hm[j];
@@ -294,6 +316,29 @@ __global__ __launch_bounds__(256) void copy_out_kernel(CopyArgs a) {
     if (a.user.niter) a.user.niter[i] = a.arena.niter[j];
     if (a.user.flags) a.user.flags[i] = a.arena.flags[j];
   }
+}
+
+// Arm one ring slot: descriptor, remaining count, then the claim word
+// (the request's tag, nothing handed out), then the class's armed count.
+// Runs after the request's copy-in on the same stream, so a wave that sees
+// the new claim word also sees the request's cells.
+__global__ __launch_bounds__(64) void arm_kernel(ArmArgs a) {
+  if (threadIdx.x != 0) return;
+  __hip_atomic_store(&a.meta->seq, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __hip_atomic_store(&a.meta->off, a.off, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&a.meta->n, a.n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&a.meta->level, a.level, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(reinterpret_cast<uint64_t*>(&a.meta->dt),
+                     (uint64_t)__double_as_longlong(a.dt), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(a.remaining, int32_t(a.n), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __hip_atomic_store(&a.meta->seq, a.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(a.claimed, (unsigned long long)(a.seq & 0xffffffffull) << 32,
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __hip_atomic_fetch_add(a.staged, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 }  // namespace
@@ -329,6 +374,11 @@ hipError_t launch_copy_in(const CopyArgs& a, hipStream_t s) {
 
 hipError_t launch_copy_out(const CopyArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(copy_out_kernel, dim3(copy_grid(a.user.n)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_arm(const ArmArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(arm_kernel, dim3(1), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 

@@ -182,11 +182,12 @@ MIXED_TOL = 1e-4
 MIXED_WELL = 1e-6
 
 
-def check_mixed_bar(gpu, ref, cells, dt, onet, opar, label=""):
+def check_mixed_bar(gpu, ref, cells, dt, onet, opar, label="", bar=True):
     """The mixed bar against the binary64 reference: p99 <= MIXED_TOL on
     every output, and max <= MIXED_TOL over the cells determined to
     binary32-coefficient accuracy; the cells beyond MIXED_TOL are counted.
-    Conservation holds to round-off (the update is binary64)."""
+    With bar=False the same figures are only printed.  Conservation holds
+    to round-off (the update is binary64) in either case."""
     errs, exc = compare(gpu, ref)
     n = ref["nsub"].shape[0]
     report(errs, exc, n, label, gpu, ref, cells)
@@ -195,7 +196,8 @@ def check_mixed_bar(gpu, ref, cells, dt, onet, opar, label=""):
         e = e[valid]
         print(f"[mixed] {label} {k}: median {np.median(e):.2e} p99 {np.percentile(e, 99):.2e} "
               f"max {np.max(e):.2e} beyond 1e-4: {int((e > MIXED_TOL).sum())}", flush=True)
-        assert np.percentile(e, 99) <= MIXED_TOL, (label, k, float(np.percentile(e, 99)))
+        if bar:
+            assert np.percentile(e, 99) <= MIXED_TOL, (label, k, float(np.percentile(e, 99)))
     sens = oracle.step_sensitivity(cells, dt, ref, onet, opar, host_threads())
     c32 = oracle.coefficient_sensitivity(cells, dt, ref, onet, opar, host_threads())
     worst = np.where(valid, worst_of(errs, n), 0.0)
@@ -204,7 +206,7 @@ def check_mixed_bar(gpu, ref, cells, dt, onet, opar, label=""):
           f"to binary32-coefficient accuracy: {int(well.sum())}, max err there "
           f"{worst[well].max() if well.any() else 0:.2e}; the rest: max "
           f"{worst[valid & ~well].max() if (valid & ~well).any() else 0:.2e}", flush=True)
-    if well.any():
+    if bar and well.any():
         i = int(np.argmax(np.where(well, worst, 0.0)))
         assert worst[well].max() <= MIXED_TOL, (label, "determined cell beyond 1e-4", i, worst[i])
     s = gpu["y_h"] + 2 * gpu["y_h2"] + gpu["y_hp"] + gpu["y_hm"]

@@ -84,3 +84,38 @@ def test_hii_region_inputs_are_valid():
     ionised = c["y_e"] > 0.5
     assert 0.2 < ionised.mean() < 0.6          # sphere of 2.67 pc in a 6 pc box: ~0.37
     assert np.all(c["n_euv"][~ionised] < c["n_euv"][ionised].min())
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """sizeof and field offsets of every ABI struct, from the header through
+    a C compiler, equal the binding's ctypes layouts."""
+    import paper_2604_21438_amd as sfc
+    structs = {"sfc_request": sfc.SfcRequest, "sfc_result": sfc.SfcResult,
+               "sfc_cells": sfc.SfcCells, "sfc_network": sfc.SfcNetwork,
+               "sfc_params": sfc.SfcParams}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "sfchem.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = str(tmp_path / "layout")
+    import subprocess
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src),
+                           "-o", exe])
+    out = dict(line.rsplit(" ", 1) for line in subprocess.check_output([exe], text=True).splitlines())
+    for cname, py in structs.items():
+        assert int(out[f"{cname} size"]) == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(out[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
+
+
+def test_served_calls_reject_bad_arguments_without_device():
+    import paper_2604_21438_amd as sfc
+    L = sfc.lib()
+    t = C.c_uint64()
+    assert L.sfc_chem_submit(None, None, C.byref(t)) == sfc.E_INVAL
+    assert L.sfc_chem_fetch(None, 1, None, None) == sfc.E_INVAL
+    assert L.sfc_chem_release(None, 1) == sfc.E_INVAL

@@ -277,3 +277,141 @@ def test_served_amr_chain_matches_plain():
         finally:
             served.close()
             plain.close()
+
+
+def test_served_resident_keys_match_plain():
+    """The same 4-level hierarchy with each level's blocks resident under a
+    block key: the first substep uploads the cells, every later one
+    continues from the arena (no copy-in, no copy-out), the finest level's
+    substeps are all submitted at once (they run one after the other), and
+    the coarsest level writes its last substep back.  Fetched results are
+    bitwise the plain step's, level by level, in both precisions."""
+    import time
+    import torch
+    sfc = _sfc()
+    levels = W.gmc_levels(target_cells=40000, base_side=16)
+    nl = len(levels)
+    for prec in (sfc.FP64, sfc.MIXED):
+        plain = sfc.Context(dust_factor=1.0, z_default=0.1)
+        served = sfc.Context(dust_factor=1.0, z_default=0.1, served_budget_bytes=64 * MIB)
+        try:
+            ref = [sfc.to_device(lv["cells"]) for lv in levels]
+            for L in range(nl):
+                for _ in range(2 ** L):
+                    plain.step(ref[L], levels[L]["dt"], prec)
+            torch.cuda.synchronize()
+            up = [sfc.to_device(lv["cells"]) for lv in levels]
+            torch.cuda.synchronize()
+            print(f"[served] resident keys, precision {prec}", flush=True)
+            key = [1000 + L for L in range(nl)]
+            last = [None] * nl
+            # finest level: every substep at once
+            fin = nl - 1
+            for s in range(2 ** fin):
+                last[fin] = served.submit(up[fin] if s == 0 else None, levels[fin]["dt"], prec,
+                                          level=fin, block_key=key[fin], resume=s > 0)
+            remaining = [2 ** L for L in range(nl)]
+            remaining[fin] = 0
+            inflight = [None] * nl
+            deadline = time.monotonic() + 120.0
+            while any(remaining) or any(t is not None for t in inflight):
+                assert time.monotonic() < deadline
+                for L in range(nl - 1):
+                    if inflight[L] is not None and served.poll(inflight[L]) is not None:
+                        inflight[L] = None
+                    if inflight[L] is None and remaining[L] > 0:
+                        first = remaining[L] == 2 ** L
+                        lastone = remaining[L] == 1
+                        wb = lastone and L == 0
+                        inflight[L] = served.submit(
+                            up[L] if (first or wb) else None, levels[L]["dt"], prec, level=L,
+                            block_key=key[L], resume=not first, writeback=wb)
+                        last[L] = inflight[L]
+                        remaining[L] -= 1
+                time.sleep(200e-6)
+            served.drain()
+            out = []
+            for L in range(nl):
+                dst = {k: torch.empty_like(v) for k, v in ref[L].items()
+                       if k not in ("nh", "n_euv", "n_fuv", "zmet")}
+                assert served.fetch(last[L], dst)
+                out.append(dst)
+            torch.cuda.synchronize()
+            for L in range(nl):
+                a = {k: v.cpu().numpy() for k, v in out[L].items()}
+                b = {k: v.cpu().numpy() for k, v in ref[L].items()}
+                _same(a, b, f"resident level {L} precision {prec}")
+            wb = {k: v.cpu().numpy() for k, v in up[0].items()}
+            _same(wb, {k: v.cpu().numpy() for k, v in ref[0].items()}, "write-back level 0")
+            # an older ticket of a key can no longer be fetched; release frees
+            with pytest.raises(sfc.SfcError, match=r"\(-7\)"):
+                served.fetch(last[fin] - 1, out[fin])
+            for k in key:
+                served.release(k)
+            with pytest.raises(sfc.SfcError, match=r"\(-7\)"):
+                served.fetch(last[0], out[0])
+            with pytest.raises(sfc.SfcError, match=r"\(-1\)"):
+                served.release(key[0])
+        finally:
+            served.close()
+            plain.close()
+
+
+def test_served_small_ring_reuses_slots():
+    """Rings of 4 slots per class (SFC_SERVE_RING=4) and 48 requests of both
+    precisions submitted at once: every slot is armed again many times
+    while waves that claimed its earlier request may still be about.  Each
+    result is bitwise the plain step's."""
+    import os
+    import torch
+    sfc = _sfc()
+    reqs = _requests(48, max_blocks=3, seed_offset=9)
+    prec = [sfc.FP64 if i % 2 else sfc.MIXED for i in range(len(reqs))]
+    old = os.environ.get("SFC_SERVE_RING")
+    os.environ["SFC_SERVE_RING"] = "4"
+    try:
+        ctx = sfc.Context(served_budget_bytes=64 * MIB)
+    finally:
+        if old is None:
+            del os.environ["SFC_SERVE_RING"]
+        else:
+            os.environ["SFC_SERVE_RING"] = old
+    try:
+        served = _run_served(ctx, reqs, prec, "ring of 4 slots")
+        for i, r in enumerate(reqs):
+            t = sfc.to_device(r["cells"])
+            ctx.step(t, r["dt"], prec[i])
+            torch.cuda.synchronize()
+            _same(served[i], {k: v.cpu().numpy() for k, v in t.items()}, f"request {i} ring 4")
+    finally:
+        ctx.close()
+
+
+def test_served_waits_for_producer_stream():
+    """Inputs written by a kernel still queued on another stream when the
+    request is submitted (sync=False with that stream named): the copy-in
+    waits for it, and the result is bitwise the plain step's."""
+    import torch
+    sfc = _sfc()
+    reqs = _requests(3, max_blocks=4, seed_offset=10)
+    ctx = sfc.Context(served_budget_bytes=64 * MIB)
+    try:
+        side = torch.cuda.Stream()
+        for i, r in enumerate(reqs):
+            pristine = sfc.to_device(r["cells"])
+            buf = {k: torch.zeros_like(v) for k, v in pristine.items()}
+            torch.cuda.synchronize()
+            with torch.cuda.stream(side):
+                torch.cuda._sleep(20_000_000)  # keep the copies below queued for a while
+                for k, v in pristine.items():
+                    buf[k].copy_(v)
+            t = ctx.submit(buf, r["dt"], sfc.FP64, sync=False, stream=side)
+            ctx.drain()
+            assert ctx.poll(t)["status"] == 0
+            torch.cuda.synchronize()
+            ctx.step(pristine, r["dt"], sfc.FP64)
+            torch.cuda.synchronize()
+            _same({k: v.cpu().numpy() for k, v in buf.items()},
+                  {k: v.cpu().numpy() for k, v in pristine.items()}, f"request {i} producer stream")
+    finally:
+        ctx.close()
