@@ -81,6 +81,30 @@ def relerr(a, b, floor=1e-20):
                 median=float(np.nanmedian(e)), frac_above_1e9=float(np.mean(e > 1e-9)))
 
 
+def worst_rel(out, ref, idx, floor=1e-20):
+    """Largest relative error of each sampled cell over the outputs (y_H by
+    the binary64 bar: within 4 ulp of 1 absolute counts as exact)."""
+    w = np.zeros(len(idx))
+    for k in ("y_h2", "y_e", "y_h", "y_hp", "y_hm", "tgas", "tdust"):
+        d = np.abs(out[k][idx] - ref[k])
+        e = d / np.maximum(np.abs(ref[k]), floor)
+        if k == "y_h":
+            e = np.where(d <= 4 * np.finfo(float).eps, 0.0, e)
+        w = np.maximum(w, np.nan_to_num(e, nan=np.inf))
+    return w
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def pct(a, q):
     return float(np.percentile(np.asarray(a, np.float64), q))
 
@@ -155,12 +179,39 @@ def served_leg(args, sfc, W, torch):
     def snapshot():
         torch.cuda.synchronize()
         return {k: torch.cat([b[k] for b in bufs]).cpu().numpy()
-                for k in ("y_h2", "y_e", "y_h", "y_hp", "y_hm", "tgas", "tdust")}
+                for k in ("y_h2", "y_e", "y_h", "y_hp", "y_hm", "tgas", "tdust", "nsub")}
+
+    # the plain path on the same cells at its best: every request of one
+    # AMR level (one dt) concatenated into one array, one sfc_chem_step per
+    # level, levels one after the other
+    by_level = {}
+    for b, r in zip(bufs, reqs):
+        by_level.setdefault(r["level"], []).append((b, r["dt"]))
+    batched = {L: ({k: torch.cat([b[k] for b, _ in lst]) for k in bufs[0]}, lst[0][1])
+               for L, lst in sorted(by_level.items())}
+    bprist = {L: {k: c[k].clone() for k in STATE_KEYS} for L, (c, _) in batched.items()}
+
+    def plain_batched(prec, label):
+        for L, (c, _) in batched.items():
+            for k in STATE_KEYS:
+                c[k].copy_(bprist[L][k])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for L, (c, dt_l) in batched.items():
+            ctx.step(c, dt_l, prec)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ns = int(torch.cat([c["nsub"] for c, _ in batched.values()]).to(torch.int64).sum())
+        log(f"[bench] served/{label}: {len(batched)} launches, {total} cells in {el:.3f} s")
+        return dict(value=total / el, seconds=el, launches=len(batched),
+                    roofline_frac=FLOP_PER_SUBCYCLE * ns / el / PEAK_FP64_VALU)
 
     el = plain(sfc.FP64, "plain fp64")
     out["plain_fp64"] = dict(value=plain_cells / el, seconds=el, requests=m, cells=plain_cells)
     el = plain(sfc.MIXED, "plain mixed")
     out["plain_mixed"] = dict(value=plain_cells / el, seconds=el, requests=m, cells=plain_cells)
+    out["plain_fp64_by_level"] = plain_batched(sfc.FP64, "plain fp64, one launch per level")
+    out["plain_mixed_by_level"] = plain_batched(sfc.MIXED, "plain mixed, one launch per level")
     # binary64 reference for the accuracy of the served mixed results
     sref = served(sfc.FP64, None, "served_fp64 reference")
     ref = snapshot()
@@ -169,9 +220,13 @@ def served_leg(args, sfc, W, torch):
         got = snapshot()
         if prec == sfc.MIXED:
             mixed_ref = got
+        # algorithmic binary64-equivalent FLOP of the drained work over the
+        # makespan, against the binary64 VALU peak
+        cap["roofline_frac"] = (FLOP_PER_SUBCYCLE * float(got["nsub"].astype(np.int64).sum()) /
+                                cap["makespan_s"] / PEAK_FP64_VALU)
         leg = dict(all_queued=cap)
         if prec == sfc.MIXED:
-            leg["vs_fp64"] = {k: relerr(got[k], ref[k]) for k in got}
+            leg["vs_fp64"] = {k: relerr(got[k], ref[k]) for k in got if k != "nsub"}
         rate = args.served_load * cap["value"] / sizes.mean()
         arr = W.poisson_arrivals(len(reqs), rate)
         leg["poisson"] = dict(load=args.served_load, rate_req_per_s=rate,
@@ -179,6 +234,10 @@ def served_leg(args, sfc, W, torch):
         out[name] = leg
     out["served_mixed_vs_plain_fp64_throughput"] = (out["served_mixed"]["all_queued"]["value"] /
                                                     out["plain_fp64"]["value"])
+    out["served_mixed_vs_plain_fp64_by_level"] = (out["served_mixed"]["all_queued"]["value"] /
+                                                  out["plain_fp64_by_level"]["value"])
+    out["served_fp64_vs_plain_fp64_by_level"] = (out["served_fp64"]["all_queued"]["value"] /
+                                                 out["plain_fp64_by_level"]["value"])
     ctx.close()
     # admission under a budget far below the workload's arena need: requests
     # wait for slots and memory while earlier ones drain
@@ -191,7 +250,8 @@ def served_leg(args, sfc, W, torch):
         tight["budget_mib"] = args.served_tight_budget_mib
         tight["arena_need_mib"] = total * 108 / 2 ** 20
         tight["bitwise_equal_to_8gib_budget"] = bool(all(
-            np.array_equal(got[k].view(np.int64), mixed_ref[k].view(np.int64)) for k in got))
+            np.array_equal(got[k].view(np.int64), mixed_ref[k].view(np.int64))
+            for k in got if k != "nsub") and np.array_equal(got["nsub"], mixed_ref["nsub"]))
         out["served_mixed_tight_budget"] = tight
         ctx.close()
     return out
@@ -379,8 +439,103 @@ def gmc_leg(args, sfc, W, torch):
                                                            p99=pct(lat, 99) * 1e3,
                                                            max=float(np.max(lat)) * 1e3))
             log(f"[bench] gmc factor {factor:g} {pname}: served {el:.2f} s")
+            # the same with each level's state resident under a block key:
+            # the first substep uploads, the others continue in the arena
+            # (no copy-in, no copy-out); the results are fetched at the end
+            restore()
+            remaining = [2 ** L for L in range(nl)]
+            inflight = [None] * nl
+            last = [None] * nl
+            lat = []
+            t0 = time.perf_counter()
+            while any(remaining) or any(t is not None for t in inflight):
+                for L in range(nl):
+                    if inflight[L] is not None:
+                        r = ctx.poll(inflight[L])
+                        if r is not None:
+                            lat.append(r["t_done"] - r["t_submit"])
+                            inflight[L] = None
+                    if inflight[L] is None and remaining[L] > 0:
+                        first = remaining[L] == 2 ** L
+                        inflight[L] = ctx.submit(bufs[L] if first else None, levels[L]["dt"],
+                                                 prec, level=L, sync=False,
+                                                 block_key=1 + L, resume=not first)
+                        last[L] = inflight[L]
+                        remaining[L] -= 1
+                time.sleep(100e-6)
+            for L in range(nl):
+                ctx.fetch(last[L], bufs[L])
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            for L in range(nl):
+                ctx.release(1 + L)
+            legs[f"served_{pname}_resident"] = dict(
+                value=updates / el, seconds=el,
+                latency_ms=dict(p50=pct(lat, 50) * 1e3, p99=pct(lat, 99) * 1e3,
+                                max=float(np.max(lat)) * 1e3))
+            log(f"[bench] gmc factor {factor:g} {pname}: served, resident blocks {el:.2f} s")
         ctx.close()
         out[f"dust_factor_{factor:g}"] = legs
+    return out
+
+
+def grid256_leg(args, sfc, W, torch):
+    """The 256^3 population (log-normal n_H with an n^-1.5 tail, 8 point
+    sources, Z = 1, dust factor 100, dt = 10 kyr): one binary64 and one mixed
+    step over all cells, timed with events after a warm-up step, and the
+    error of both against the CPU reference on a seeded sample of cells."""
+    import oracle
+    cells, dt = W.grid256(side=args.grid256_side)
+    n = cells["nh"].shape[0]
+    log(f"[bench] grid256: {n} cells")
+    prist = sfc.to_device(cells, outputs=False)
+    work = sfc.to_device(cells)
+    out = dict(workload=f"{args.grid256_side}^3 log-normal density (mu = ln 100, sigma = 2) with "
+                        "an n^-1.5 tail above 1e4, 8 point sources, Z = 1, dust factor 100, "
+                        "dt = 10 kyr", cells=n, dt_s=dt)
+    res = {}
+    for prec, name in ((sfc.FP64, "fp64"), (sfc.MIXED, "mixed")):
+        ctx = sfc.Context(dust_factor=100.0)
+        times = []
+        for rep in range(2):
+            for k in STATE_KEYS:
+                work[k].copy_(prist[k])
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ctx.step(work, dt, prec)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1) * 1e-3)
+        ctx.close()
+        o = {k: v.cpu().numpy() for k, v in work.items()}
+        res[name] = o
+        ns = o["nsub"].astype(np.int64)
+        s = times[-1]
+        out[name] = dict(value=n / s, seconds=s, nsub=stats(ns),
+                         roofline_frac=FLOP_PER_SUBCYCLE * float(ns.sum()) / s / PEAK_FP64_VALU)
+        log(f"[bench] grid256 {name}: {s:.3f} s, {n / s:.3e} cell-updates/s")
+    out["mixed_speedup_vs_fp64"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
+    if not args.no_cpu:
+        m = min(args.grid256_sample, n)
+        sub, idx = W.subsample(cells, m, seed=77)
+        threads = max(1, min(16, os.cpu_count() or 1))
+        p = oracle.default_params(dust_cap=1e6)
+        t0 = time.perf_counter()
+        ref = oracle.li_step(sub, dt, params=p, nthreads=threads)
+        log(f"[bench] grid256 reference on {m} cells: {time.perf_counter() - t0:.1f} s")
+        for name in ("fp64", "mixed"):
+            errs = {k: relerr(res[name][k][idx], ref[k]) for k in
+                    ("y_h2", "y_e", "y_h", "y_hp", "y_hm", "tgas", "tdust")}
+            w = np.zeros(m)
+            for k in ("y_h2", "y_e", "y_h", "y_hp", "y_hm", "tgas", "tdust"):
+                e = np.abs(res[name][k][idx] - ref[k]) / np.maximum(np.abs(ref[k]), 1e-20)
+                w = np.maximum(w, np.nan_to_num(e, nan=np.inf))
+            out[f"{name}_vs_reference"] = dict(
+                sample=m, per_output=errs, cells_beyond_1e9=int((w > 1e-9).sum()),
+                cells_beyond_1e4=int((w > 1e-4).sum()),
+                nsub_mismatch=int((res[name]["nsub"][idx] != ref["nsub"]).sum()))
     return out
 
 
@@ -413,6 +568,10 @@ def main():
     ap.add_argument("--served-tight-budget-mib", type=int, default=64,
                     help="second served budget that forces queueing (0 skips it)")
     ap.add_argument("--cpu-cells", type=int, default=32768)
+    ap.add_argument("--grid256-side", type=int, default=256,
+                    help="side of the log-normal / point-source grid leg (0 skips it)")
+    ap.add_argument("--grid256-sample", type=int, default=65536,
+                    help="cells of that leg checked against the CPU reference")
     ap.add_argument("--cells", type=int, default=None, help="fewer cells (testing only)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run three device-to-device copies of MIB MiB (a kernel of "
@@ -520,7 +679,7 @@ def main():
             "traffic": measured_traffic(),
             "traffic_unit": "bytes per step (both launches)",
             "algorithmic_bytes": n * BYTES_PER_CELL,
-            "kernel": "li_step_kernel<double, false>",
+            "kernel": "li_step_kernel<double>",
             "launches_per_step": 2,
             "flop_per_subcycle": FLOP_PER_SUBCYCLE,
             "subcycles_per_step": d64["subcycles"],
@@ -571,6 +730,10 @@ def main():
     if not args.no_collapse:
         result["collapse"] = collapse_leg(sfc)
 
+    # ---- 256^3 log-normal population, binary64 and mixed ----
+    if args.grid256_side > 0:
+        result["grid256"] = grid256_leg(args, sfc, W, torch)
+
     # ---- served form: AMR-shaped requests with Poisson arrivals ----
     if not args.no_served:
         result["served"] = served_leg(args, sfc, W, torch)
@@ -584,6 +747,7 @@ def main():
         import oracle
         m = min(args.cpu_cells, n)
         sub, idx = W.subsample(cells, m, seed=99)
+        # the host's share of one GPU on the benchmark machines is 16 cores
         threads = max(1, min(16, os.cpu_count() or 1))
         log(f"[bench] cpu reference: {m} cells on {threads} threads")
         t0 = time.perf_counter()
@@ -591,15 +755,28 @@ def main():
         el = time.perf_counter() - t0
         log(f"[bench] cpu reference done in {el:.1f} s")
         result["cpu_baseline"] = {"value": m / el, "unit": "cell-updates/s", "cores": threads,
-                                  "kind": "oracle",
+                                  "kind": "oracle", "cpu_model": cpu_model(),
                                   "sample": f"{m} seeded cells of the same 128^3 population, "
                                             f"dt = 10 kyr, dust factor 1, binary64"}
+        # one core over the whole 4096-cell population (dt = 1 kyr)
+        small, dt1 = W.small_cells()
+        t0 = time.perf_counter()
+        oracle.li_step(small, dt1, nthreads=1)
+        el1 = time.perf_counter() - t0
+        result["cpu_single_core_4096_cells"] = {
+            "value": small["nh"].shape[0] / el1, "unit": "cell-updates/s", "cores": 1,
+            "seconds": el1, "workload": "16^3 = 4096 independent cells, dt = 1 kyr, dust factor 1"}
+        log(f"[bench] cpu reference, one core, 4096 cells: {el1:.1f} s")
         par = {"fp64": {k: relerr(out64[k][idx], ref[k]) for k in
                         ("y_h2", "y_e", "y_h", "y_hp", "y_hm", "tgas", "tdust")}}
         par["fp64_nsub_mismatch"] = int((out64["nsub"][idx] != ref["nsub"]).sum())
+        w64 = worst_rel(out64, ref, idx)
+        par["fp64_cells_beyond_1e9"] = int((w64 > 1e-9).sum())
         if outmx is not None:
             par["mixed"] = {k: relerr(outmx[k][idx], ref[k]) for k in
                             ("y_h2", "y_e", "y_h", "y_hp", "y_hm", "tgas", "tdust")}
+            par["mixed_cells_beyond_1e4"] = int((worst_rel(outmx, ref, idx) > 1e-4).sum())
+        par["cells"] = m
         result["parity_on_cpu_sample"] = par
 
     print(json.dumps(result))

@@ -102,6 +102,22 @@ typedef struct {
   double line_g[SFC_NLINE];      /*   de-excitation by H+H2 [cm^3/s] and by */
   double line_qn[SFC_NLINE];     /*   electrons at 100 K [cm^3/s] (~T^-1/2) */
   double line_qe100[SFC_NLINE];
+  /* Beside the solver (the paper takes these from its references; text
+   * after Table "Thermal processes"), labelled stand-ins, off by default:
+   * pe_mode 1: photoelectric efficiency with grain charging, psi =
+   *   G0 sqrt(T) / n_e, eps = 0.0487 / (1 + 4e-3 psi^0.73) + 0.0365
+   *   (T/1e4)^0.7 / (1 + 2e-4 psi), Gamma_pe = 1.3e-24 eps G0 n_H Z, and
+   *   the cooling by electron recombination on grains 4.65e-30 T^0.94
+   *   psi^beta n_e n_H Z, beta = 0.735 T^-0.068 (n_e floored at y_abs n_H
+   *   inside psi; both scaled by proc_mult[3]);
+   * shield_mode 1: H2 photodissociation times the self-shielding factor
+   *   0.965 / (1 + x/b5)^2 + 0.035 / sqrt(1 + x) exp(-8.5e-4 sqrt(1 + x)),
+   *   x = N_H2 / 5e14 cm^-2 with N_H2 = y_H2 n_H L, L = shield_len Jeans
+   *   lengths sqrt(pi k_B T / (G m_H rho)). */
+  double shield_len;             /* column length in Jeans lengths [0.5]   */
+  double shield_b5;              /* Doppler parameter [km/s] [2]           */
+  int32_t pe_mode;               /* [0]                                    */
+  int32_t shield_mode;           /* [0]                                    */
 } sfc_network;
 
 /* Numerical and physical parameters; defaults in brackets. */
@@ -121,6 +137,14 @@ typedef struct {
   int32_t dust_mode;   /* sfc_dust_mode [SFC_DUST_EVOLVE]                 */
   int32_t dispatch;    /* sfc_dispatch [SFC_DISPATCH_PROGRESS]            */
   int32_t phase_nsub;  /* PROGRESS: subcycles of the first pass, >= 1 [4096] */
+  int32_t photon_absorb; /* 1: after the update, the EUV and FUV photon
+                          densities absorbed over dt are written to
+                          sfc_cells.n_euv_out / n_fuv_out (plain path):
+                          N exp(-c~ alpha dt), alpha_EUV = sigma_EUV n_H y_H
+                          + kappa_UV rho Z, alpha_FUV = kappa_UV rho Z, with
+                          the updated y_H (Sec. 2 "Radiation components")
+                          [0] */
+  int32_t reserved;    /* must be 0 */
 } sfc_params;
 
 void sfc_network_default(sfc_network* net);
@@ -161,6 +185,9 @@ typedef struct {
   const double *nh, *n_euv, *n_fuv, *zmet;
   int32_t *nsub, *niter;
   uint32_t *flags;
+  double *n_euv_out, *n_fuv_out; /* out (optional; sfc_params.photon_absorb,
+                                    plain path only; an invalid cell copies
+                                    its inputs) */
 } sfc_cells;
 
 enum {
@@ -199,7 +226,8 @@ int sfc_chem_step(sfc_ctx* ctx, const sfc_cells* cells, double dt_seconds, int p
  * tolerance 1e-5 relaxed to 1e-3 after 10 outer iterations, 20 iterations
  * per loop; a substep that fails is halved (Eq. substep_NRchem).  Binary64.
  * Same buffers, ownership and asynchrony as sfc_chem_step; nsub receives
- * the accepted substeps, niter the outer iterations, flags SFC_F_NRFAIL
+ * the accepted substeps, niter every Newton iteration (outer, dust/IR and
+ * chemistry, failed substeps included), flags SFC_F_NRFAIL
  * for a cell that could not finish.  C_d is the context's (the paper runs
  * NR with the realistic value).
  * Errors: SFC_E_INVAL, SFC_E_NOMEM, SFC_E_DEVICE. */

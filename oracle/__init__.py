@@ -91,6 +91,8 @@ class Network(C.Structure):
         ("line_tul", C.c_double * NLINE), ("line_a", C.c_double * NLINE),
         ("line_g", C.c_double * NLINE), ("line_qn", C.c_double * NLINE),
         ("line_qe100", C.c_double * NLINE),
+        ("shield_len", C.c_double), ("shield_b5", C.c_double),
+        ("pe_mode", C.c_int32), ("shield_mode", C.c_int32),
     ]
 
 
@@ -101,6 +103,7 @@ class Params(C.Structure):
         ("gamma_ad", C.c_double), ("dust_cap", C.c_double), ("z_default", C.c_double),
         ("n_cyc", C.c_int32), ("n_sub_max", C.c_int32), ("newton_max", C.c_int32),
         ("ir_mode", C.c_int32), ("thermal_mode", C.c_int32), ("dust_mode", C.c_int32),
+        ("photon_absorb", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -116,6 +119,7 @@ class Cells(C.Structure):
         ("y_h", _dp), ("y_hp", _dp), ("y_hm", _dp), ("tgas", _dp),
         ("nh", _dp), ("n_euv", _dp), ("n_fuv", _dp), ("zmet", _dp),
         ("nsub", _ip), ("niter", _ip), ("flags", _up),
+        ("n_euv_out", _dp), ("n_fuv_out", _dp),
     ]
 
 
@@ -186,6 +190,7 @@ def _assign(obj, k, v):
 STATE = ("y_h2", "y_e", "eint", "tdust", "eir")
 INPUTS = ("nh", "n_euv", "n_fuv", "zmet")
 OUT_F = ("y_h", "y_hp", "y_hm", "tgas")
+PHOTON_OUT = ("n_euv_out", "n_fuv_out")
 
 
 def _ptr(a, ctype):
@@ -197,7 +202,7 @@ def _cells(arrs: dict, n: int):
     keep = {}
     c = Cells()
     c.n = n
-    for k in STATE + INPUTS + OUT_F:
+    for k in STATE + INPUTS + OUT_F + PHOTON_OUT:
         a = arrs.get(k)
         if a is not None:
             assert a.dtype == np.float64 and a.flags.c_contiguous and a.shape == (n,), k
@@ -210,7 +215,7 @@ def _cells(arrs: dict, n: int):
     return c, keep
 
 
-def _prepare(cells: dict, ir_mode: int):
+def _prepare(cells: dict, ir_mode: int, photon_absorb: int = 0):
     """Copy the inputs, allocate outputs; returns the dict the oracle writes."""
     n = int(np.asarray(cells["nh"]).shape[0])
     out = {}
@@ -224,6 +229,9 @@ def _prepare(cells: dict, ir_mode: int):
     out["nsub"] = np.zeros(n, np.int32)
     out["niter"] = np.zeros(n, np.int32)
     out["flags"] = np.zeros(n, np.uint32)
+    if photon_absorb:
+        for k in PHOTON_OUT:
+            out[k] = np.empty(n, np.float64)
     return out, n
 
 
@@ -234,7 +242,7 @@ def li_step(cells: dict, dt: float, net: Network | None = None, params: Params |
     "rcp", "rcpdn", "all", "c32"; see build)."""
     net = net or default_network()
     params = params or default_params()
-    out, n = _prepare(cells, params.ir_mode)
+    out, n = _prepare(cells, params.ir_mode, params.photon_absorb)
     c, keep = _cells(out, n)
     rc = _lib(variant=variant).orc_li_step(C.byref(net), C.byref(params), C.byref(c), float(dt),
                                             int(nthreads))
@@ -248,7 +256,7 @@ def nr_step(cells: dict, dt: float, net: Network | None = None, params: Params |
     """Newton-Raphson comparator over dt [s]; same variants as li_step."""
     net = net or default_network()
     params = params or default_params()
-    out, n = _prepare(cells, params.ir_mode)
+    out, n = _prepare(cells, params.ir_mode, params.photon_absorb)
     c, keep = _cells(out, n)
     rc = _lib(variant=variant).orc_nr_step(C.byref(net), C.byref(params), C.byref(c), float(dt),
                                             int(nthreads))
@@ -261,7 +269,7 @@ def rk_reference(cells: dict, dt: float, net: Network | None = None,
                  params: Params | None = None, step_frac: float = 1e-3) -> dict:
     net = net or default_network()
     params = params or default_params()
-    out, n = _prepare(cells, params.ir_mode)
+    out, n = _prepare(cells, params.ir_mode, params.photon_absorb)
     c, keep = _cells(out, n)
     rc = _lib().orc_rk_reference(C.byref(net), C.byref(params), C.byref(c), float(dt),
                                  float(step_frac))
@@ -313,7 +321,7 @@ def count_li(cells: dict, dt: float, idx, net=None, params=None) -> np.ndarray:
     net = net or default_network()
     params = params or default_params()
     lib = _lib(counting=True)
-    out, n = _prepare(cells, params.ir_mode)
+    out, n = _prepare(cells, params.ir_mode, params.photon_absorb)
     c, keep = _cells(out, n)
     res = np.zeros((len(idx), 6))
     buf = np.zeros(6)

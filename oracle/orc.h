@@ -59,6 +59,14 @@ typedef struct {
   double line_g[ORC_NLINE];     /* g_u / g_l                                */
   double line_qn[ORC_NLINE];    /* de-excitation by H + H2 [cm^3/s]         */
   double line_qe100[ORC_NLINE]; /* de-excitation by e at 100 K [cm^3/s], ~T^-1/2 */
+  /* The pieces the paper takes from its references beside the solver
+   * (H2 self-shielding and photoelectric heating with grain charging, the
+   * text after Table "Thermal processes"); STAND-INS, off by default. */
+  double shield_len;  /* H2 column length in Jeans lengths (shield_mode 1) */
+  double shield_b5;   /* Doppler parameter of the self-shielding fit [km/s] */
+  int32_t pe_mode;    /* 0: constant efficiency; 1: grain-charge efficiency
+                         and recombination cooling                          */
+  int32_t shield_mode;/* 0: no self-shielding; 1: local H2 column          */
 } orc_network;
 
 enum { ORC_IR_FIXED = 0, ORC_IR_EVOLVE = 1 };
@@ -81,6 +89,9 @@ typedef struct {
   int32_t ir_mode;     /* ORC_IR_FIXED / ORC_IR_EVOLVE           [FIXED] */
   int32_t thermal_mode;/* ORC_THERMAL_*                          [EVOLVE]*/
   int32_t dust_mode;   /* ORC_DUST_*                             [EVOLVE]*/
+  int32_t photon_absorb; /* 1: attenuate N_EUV, N_FUV over dt after the
+                            update (Sec. 2 "Radiation components")   [0]  */
+  int32_t reserved;
 } orc_params;
 
 /* Host structure-of-arrays cell buffers, all of length n.  In/out arrays
@@ -92,6 +103,7 @@ typedef struct {
   const double *nh, *n_euv, *n_fuv, *zmet;  /* in; zmet optional           */
   int32_t *nsub, *niter;                    /* out, optional               */
   uint32_t *flags;                          /* out, optional               */
+  double *n_euv_out, *n_fuv_out;            /* out, optional (photon_absorb) */
 } orc_cells;
 
 /* per-cell flag bits */
@@ -130,8 +142,9 @@ void orc_rate_coeffs(const orc_network* net, const orc_params* p, double T,
 
 /* Chemistry + heating/cooling sources at (y_H2, y_e, T) with T_d frozen:
  * out[0..2] = (R_H2, R_e, Q);  jac[3*i + j] = d out[i] / d (y_H2, y_e, T)[j].
- * terms[0..13] = Gamma_1..Gamma_4, Lambda_5..Lambda_13 (erg cm^-3 s^-1),
- * terms[13] = unused (gas-grain lives in the dust system). */
+ * terms[0..12] = Gamma_1..Gamma_4, Lambda_5..Lambda_13 (erg cm^-3 s^-1);
+ * terms[13] = cooling by electron recombination on grains (pe_mode 1, else
+ * 0; the gas-grain exchange Lambda_14 lives in the dust system). */
 void orc_chem_sources(const orc_network* net, const orc_params* p,
                       double y_h2, double y_e, double T, double tdust,
                       double nh, double fd, double n_euv, double n_fuv,

@@ -63,6 +63,7 @@ const double M_H = 1.67262192e-24;     /* g, mass of the H nucleus  */
 const double EV = 1.602176634e-12;     /* erg                       */
 const double C_LIGHT = 2.99792458e10;  /* cm/s                      */
 const double A_RAD = 7.5657e-15;       /* erg cm^-3 K^-4            */
+const double G_GRAV = 6.6743e-8;       /* cm^3 g^-1 s^-2            */
 const double LN10 = 2.302585092994045684;
 
 /* Appendix C constants: R_g, T_high, T_low */
@@ -205,6 +206,81 @@ static void rates(const orc_network& net, real T, real Td, const Cell& c, Rates&
 }
 
 /* ------------------------------------------------------------------ */
+/* H2 self-shielding factor f_sh as a function of (y_H2, T).  STAND-IN for
+ * the prescription the paper takes from its reference (text after Table
+ * "Thermal processes"): the self-shielding fit of Draine & Bertoldi (1996),
+ *   f_sh = 0.965 / (1 + x / b5)^2 + 0.035 / sqrt(1 + x) exp(-8.5e-4 sqrt(1 + x)),
+ * x = N_H2 / 5e14 cm^-2, b5 the Doppler parameter in km/s, with the local
+ * column N_H2 = y_H2 n_H L, L = shield_len times the Jeans length
+ * sqrt(pi k_B T / (G m_H rho)) of the cell (so L grows as sqrt(T)).
+ * Returns f_sh as a G3 with its y_H2 and T partials. */
+static G3 h2_shield(const orc_network& net, real y2, real T, const Cell& c) {
+  const real L = net.shield_len * rsqrt(3.14159265358979323846 * K_B * T / (G_GRAV * M_H * c.rho));
+  const real dxdy = c.n * L / 5.0e14;
+  const real x = y2 * dxdy;
+  const real dxdT = x / (2.0 * T);
+  const real b5 = net.shield_b5;
+  const real u = 1.0 + x / b5;
+  const real sq = rsqrt(1.0 + x);
+  const real ex = rexp(-8.5e-4 * sq);
+  const real f = 0.965 / (u * u) + 0.035 / sq * ex;
+  /* d/dx: -2 0.965 / (b5 u^3) + 0.035 ex (-1/sq^2 - 8.5e-4 / sq) / (2 sq) */
+  const real dfdx = -2.0 * 0.965 / (b5 * u * u * u) +
+                    0.035 * ex * (-1.0 / (sq * sq) - 8.5e-4 / sq) / (2.0 * sq);
+  return G3{f, dfdx * dxdy, 0.0, dfdx * dxdT};
+}
+
+/* Photoelectric heating with grain charging and the cooling by electron
+ * recombination on grains, as functions of (y_e, T).  STAND-IN for the
+ * rates the paper takes from its reference (Table "Thermal processes",
+ * process 4, and the text after it): the efficiency of Bakes & Tielens
+ * (1994) in the form of Wolfire et al. (2003) with charging parameter
+ * psi = G0 sqrt(T) / n_e,
+ *   eps = 0.0487 / (1 + 4e-3 psi^0.73) + 0.0365 (T / 1e4)^0.7 / (1 + 2e-4 psi),
+ *   Gamma_pe = 1.3e-24 eps G0 n_H f_d,
+ *   Lambda_rec = 4.65e-30 T^0.94 psi^beta n_e n_H f_d,  beta = 0.735 T^-0.068.
+ * Reading: n_e is floored at y_abs n_H inside psi (psi stays finite in
+ * neutral gas; the floor is the abundance floor of the timescales). */
+static void photoelectric(const orc_params& p, real ye, real T, const Cell& c, G3& heat,
+                          G3& rec) {
+  if (!(c.g0 > real(0.0))) { /* no FUV field: no photoelectrons, neutral grains */
+    heat = cst(0.0);
+    rec = cst(0.0);
+    return;
+  }
+  const bool floored = ye < real(p.y_abs);
+  const real yef = floored ? real(p.y_abs) : ye;
+  const real ne = yef * c.n;
+  const real psi = c.g0 * rsqrt(T) / ne;
+  const real dpsi_dye = floored ? real(0.0) : -psi / ye;
+  const real dpsi_dT = psi / (2.0 * T);
+  const real p73 = rpow(psi, 0.73);
+  const real a1 = 1.0 + 4.0e-3 * p73;
+  const real tt = rpow(T / 1.0e4, 0.7);
+  const real b1 = 1.0 + 2.0e-4 * psi;
+  const real eps = 0.0487 / a1 + 0.0365 * tt / b1;
+  /* d eps / d psi and the explicit T dependence through (T/1e4)^0.7 */
+  const real deps_dpsi = -0.0487 * (4.0e-3 * 0.73 * p73 / psi) / (a1 * a1) -
+                         0.0365 * tt * 2.0e-4 / (b1 * b1);
+  const real deps_dT = 0.0365 * (0.7 * tt / T) / b1;
+  const real ch = 1.3e-24 * c.g0 * c.n * c.fd;
+  heat = G3{ch * eps, 0.0, ch * deps_dpsi * dpsi_dye,
+            ch * (deps_dpsi * dpsi_dT + deps_dT)};
+  /* Lambda_rec = 4.65e-30 n_H^2 f_d y_e T^0.94 psi^beta */
+  const real beta = 0.735 * rpow(T, -0.068);
+  const real dbeta_dT = -0.068 * beta / T;
+  const real lpsi = rlog(psi);
+  const real pb = rexp(beta * lpsi);
+  const real t94 = rpow(T, 0.94);
+  const real cr = 4.65e-30 * c.n * c.n * c.fd;
+  const real v = cr * ye * t94 * pb;
+  /* d/dy_e: ye psi^beta with psi ~ 1/y_e (unfloored): (1 - beta) psi^beta */
+  const real dv_dye = cr * t94 * pb * (1.0 + ye * beta * dpsi_dye / psi);
+  const real dv_dT = v * (0.94 / T + dbeta_dT * lpsi + beta * dpsi_dT / psi);
+  rec = G3{v, 0.0, dv_dye, dv_dT};
+}
+
+/* ------------------------------------------------------------------ */
 /* Chemistry and gas heating/cooling, Tables "Chemical reactions" and  */
 /* "Thermal processes".  Returns R_H2, R_e [1/s] and Q = Gamma - Lambda */
 /* [erg cm^-3 s^-1] with partials w.r.t. (y_H2, y_e, T); T_d frozen.   */
@@ -254,7 +330,9 @@ static void chem(const orc_network& net, const orc_params& p, real y2, real ye, 
   G3 r7 = n * (k[7] * yH2 * yH2);          /* 2H2 -> 2H + H2             */
   G3 r8 = n * (k[8] * yH);                 /* grains: dy_H2/dt = k n y_H */
   G3 r9 = k[9] * yH;                       /* photoionisation            */
-  G3 r10 = k[10] * yH2;                    /* photodissociation          */
+  /* photodissociation, with H2 self-shielding in shield_mode 1 */
+  const G3 shield = net.shield_mode == 1 ? h2_shield(net, y2, T, c) : cst(1.0);
+  G3 r10 = k[10] * (shield * yH2);
   G3 r11 = k[11] * yH;                     /* cosmic rays                */
 
   o.rh2 = r23 + r5 + r6 + r8 - r4 - r7 - r10;
@@ -284,8 +362,18 @@ static void chem(const orc_network& net, const orc_params& p, real y2, real ye, 
    * references): fixed heat per photoionisation and photodissociation,
    * photoelectric heating with constant efficiency. */
   G3 gam2 = (pm[1] * net.heat_euv_ev * EV * n) * (k[9] * yH);
-  G3 gam3 = (pm[2] * net.heat_h2diss_ev * EV * n) * (k[10] * yH2);
+  G3 gam3 = (pm[2] * net.heat_h2diss_ev * EV * n) * (k[10] * (shield * yH2));
+  /* Gamma_4: constant efficiency (pe_mode 0), or grain-charge efficiency
+   * with the cooling by electron recombination on the charged grains
+   * (pe_mode 1; both scaled by the multiplier of process 4) */
   G3 gam4 = cst(pm[3] * net.pe_coef * net.pe_eps * c.g0 * n * c.fd);
+  G3 lamrec = cst(0.0);
+  if (net.pe_mode == 1) {
+    G3 pe_heat, pe_rec;
+    photoelectric(p, ye, T, c, pe_heat, pe_rec);
+    gam4 = pm[3] * pe_heat;
+    lamrec = pm[3] * pe_rec;
+  }
 
   /* ---- cooling ---- */
   const real n2 = n * n;
@@ -369,10 +457,10 @@ static void chem(const orc_network& net, const orc_params& p, real y2, real ye, 
   }
 
   o.q = gam1 + gam2 + gam3 + gam4 -
-        (lam5 + lam6 + lam7 + lam8 + lam9 + lam10 + lam11 + lam12 + lam13);
-  G3 all[13] = {gam1, gam2, gam3, gam4, lam5, lam6, lam7, lam8, lam9, lam10, lam11, lam12, lam13};
-  for (int i = 0; i < 13; ++i) o.terms[i] = all[i].v;
-  o.terms[13] = 0.0;
+        (lam5 + lam6 + lam7 + lam8 + lam9 + lam10 + lam11 + lam12 + lam13 + lamrec);
+  G3 all[14] = {gam1, gam2, gam3, gam4, lam5, lam6, lam7, lam8, lam9, lam10, lam11, lam12, lam13,
+                lamrec};
+  for (int i = 0; i < 14; ++i) o.terms[i] = all[i].v;
 
   /* temperature clamp: no dependence outside the fitted range */
   o.rh2.t = o.rh2.t * dTr;
@@ -794,9 +882,26 @@ static void load(const orc_params& p, const orc_cells& cs, int64_t i, CellIn& ci
   s.Eir = (p.ir_mode == ORC_IR_EVOLVE) ? real(cs.eir[i]) : real(A_RAD * tc4 / p.c_red);
 }
 
+/* EUV and FUV photons absorbed over the hydro step after the update (Sec. 2
+ * "Radiation components": absorptions are accounted for after the
+ * abundances and temperatures are updated).  The absorption term of the
+ * reduced-speed-of-light transport, dN/dt = -c~ alpha N, integrated
+ * exactly over dt with the absorbers of the updated state: alpha_EUV =
+ * sigma_EUV n_H y_H + kappa_UV rho f_d (photoionisation and dust),
+ * alpha_FUV = kappa_UV rho f_d (dust).  STAND-IN for the scheme of the
+ * paper's reference (its Appendix C is not reproduced in the paper). */
+static void absorb_photons(const orc_network& net, const orc_params& p, const Cell& c, real yh,
+                           double dt, real& neuv, real& nfuv) {
+  const real ctil = p.c_red * C_LIGHT;
+  const real a_dust = net.kappa_uv * c.rho * c.fd;
+  const real a_euv = net.sigma_euv * c.n * rmax(yh, real(0.0)) + a_dust;
+  neuv = c.n_euv * rexp(-ctil * a_euv * dt);
+  nfuv = c.n_fuv * rexp(-ctil * a_dust * dt);
+}
+
 static void store(const orc_network& net, const orc_params& p, const orc_cells& cs, int64_t i,
                   const Cell& c, const State& s, bool isothermal, real Tiso, int nsub, int nit,
-                  uint32_t fl) {
+                  uint32_t fl, double dt) {
   cs.y_h2[i] = rval(s.y2);
   cs.y_e[i] = rval(s.ye);
   cs.eint[i] = rval(s.E);
@@ -814,6 +919,12 @@ static void store(const orc_network& net, const orc_params& p, const orc_cells& 
   if (cs.nsub) cs.nsub[i] = nsub;
   if (cs.niter) cs.niter[i] = nit;
   if (cs.flags) cs.flags[i] = fl;
+  if (p.photon_absorb == 1 && (cs.n_euv_out || cs.n_fuv_out)) {
+    real neuv, nfuv;
+    absorb_photons(net, p, c, yh, dt, neuv, nfuv);
+    if (cs.n_euv_out) cs.n_euv_out[i] = rval(neuv);
+    if (cs.n_fuv_out) cs.n_fuv_out[i] = rval(nfuv);
+  }
 }
 
 static void store_invalid(const orc_cells& cs, int64_t i) {
@@ -825,6 +936,9 @@ static void store_invalid(const orc_cells& cs, int64_t i) {
   if (cs.nsub) cs.nsub[i] = 0;
   if (cs.niter) cs.niter[i] = 0;
   if (cs.flags) cs.flags[i] = ORC_F_INVALID;
+  /* an invalid cell absorbs nothing */
+  if (cs.n_euv_out) cs.n_euv_out[i] = cs.n_euv[i];
+  if (cs.n_fuv_out) cs.n_fuv_out[i] = cs.n_fuv[i];
 }
 
 /* ------------------------------------------------------------------ */
@@ -957,7 +1071,7 @@ static void li_cell(const orc_network& net, const orc_params& p, const orc_cells
     if (last) break;
     rem = rem - h;
   }
-  store(net, p, cs, i, c, s, iso, Tiso, nsub, nit, fl);
+  store(net, p, cs, i, c, s, iso, Tiso, nsub, nit, fl, dt);
 }
 
 /* ------------------------------------------------------------------ */
@@ -1060,11 +1174,11 @@ static bool nr_inner(const orc_network& net, const orc_params& p, const Cell& c,
   return true;
 }
 
-static bool nr_substep(const orc_network& net, const orc_params& p, const Cell& c, State& s,
-                       real dts, bool iso, real Tiso, bool dust_on, int& outer) {
+static bool nr_substep_iter(const orc_network& net, const orc_params& p, const Cell& c,
+                            State& s, real dts, bool iso, real Tiso, bool dust_on, int& outer,
+                            int& idust, int& ichem) {
   State s0 = s;
   NRState g{s.y2, s.ye, iso ? Tiso : s.E / cv_of(p, c, s.y2, s.ye), s.Td, s.Eir};
-  int idust = 0, ichem = 0;
   if (iso) {
     real Gv;
     if (!nr_inner(net, p, c, s0, dts, Tiso, 1e-5, dust_on, g, Gv, idust, ichem)) return false;
@@ -1113,6 +1227,17 @@ static bool nr_substep(const orc_network& net, const orc_params& p, const Cell& 
   return false;
 }
 
+/* One substep; `iters` counts every Newton iteration: the outer ones and
+ * the inner dust/IR and chemistry iterations (the count reported per cell,
+ * so that equal counts mean the same convergence decisions). */
+static bool nr_substep(const orc_network& net, const orc_params& p, const Cell& c, State& s,
+                       real dts, bool iso, real Tiso, bool dust_on, int& iters) {
+  int outer = 0, idust = 0, ichem = 0;
+  const bool ok = nr_substep_iter(net, p, c, s, dts, iso, Tiso, dust_on, outer, idust, ichem);
+  iters += outer + idust + ichem;
+  return ok;
+}
+
 static void nr_cell(const orc_network& net, const orc_params& p, const orc_cells& cs, int64_t i,
                     double dt) {
   CellIn ci;
@@ -1155,7 +1280,7 @@ static void nr_cell(const orc_network& net, const orc_params& p, const orc_cells
       break;
     }
   }
-  store(net, p, cs, i, c, s, iso, Tiso, nsub, outer, fl);
+  store(net, p, cs, i, c, s, iso, Tiso, nsub, outer, fl, dt);
 }
 
 /* ------------------------------------------------------------------ */
@@ -1227,7 +1352,7 @@ static void rk_cell(const orc_network& net, const orc_params& p, const orc_cells
     t = t + h;
     ++nsub;
   }
-  store(net, p, cs, i, c, s, iso, Tiso, nsub, 0, fl);
+  store(net, p, cs, i, c, s, iso, Tiso, nsub, 0, fl, dt);
 }
 
 template <class F>
@@ -1296,6 +1421,10 @@ void orc_network_default(orc_network* net) {
     net->line_qn[j] = qn[j];
     net->line_qe100[j] = qe[j];
   }
+  net->shield_len = 0.5;
+  net->shield_b5 = 2.0;
+  net->pe_mode = 0;
+  net->shield_mode = 0;
 }
 
 void orc_params_default(orc_params* p) {

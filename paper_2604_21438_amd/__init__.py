@@ -41,6 +41,8 @@ class SfcNetwork(C.Structure):
         ("x_c", _d), ("x_o", _d), ("f_oiii", _d),
         ("line_tul", _d * NLINE), ("line_a", _d * NLINE), ("line_g", _d * NLINE),
         ("line_qn", _d * NLINE), ("line_qe100", _d * NLINE),
+        ("shield_len", _d), ("shield_b5", _d), ("pe_mode", C.c_int32),
+        ("shield_mode", C.c_int32),
     ]
 
 
@@ -51,6 +53,7 @@ class SfcParams(C.Structure):
         ("n_cyc", C.c_int32), ("n_sub_max", C.c_int32), ("newton_max", C.c_int32),
         ("ir_mode", C.c_int32), ("thermal_mode", C.c_int32), ("dust_mode", C.c_int32),
         ("dispatch", C.c_int32), ("phase_nsub", C.c_int32),
+        ("photon_absorb", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -60,7 +63,7 @@ _vp = C.c_void_p
 class SfcCells(C.Structure):
     _fields_ = [("n", C.c_int64)] + [(k, _vp) for k in (
         "y_h2", "y_e", "eint", "tdust", "eir", "y_h", "y_hp", "y_hm", "tgas",
-        "nh", "n_euv", "n_fuv", "zmet", "nsub", "niter", "flags")]
+        "nh", "n_euv", "n_fuv", "zmet", "nsub", "niter", "flags", "n_euv_out", "n_fuv_out")]
 
 
 class SfcRequest(C.Structure):
@@ -75,7 +78,8 @@ class SfcResult(C.Structure):
 
 
 EXPORTS = ("sfc_network_default", "sfc_params_default", "sfc_chem_init", "sfc_chem_step",
-           "sfc_chem_step_nr", "sfc_chem_submit", "sfc_chem_poll", "sfc_chem_fetch",
+           "sfc_chem_step_nr", "sfc_chem_submit", "sfc_chem_poll",
+           "sfc_chem_fetch",
            "sfc_chem_release", "sfc_chem_drain", "sfc_chem_destroy", "sfc_strerror",
            "sfc_last_error", "sfc_now")
 
@@ -152,12 +156,14 @@ class SfcError(RuntimeError):
 STATE = ("y_h2", "y_e", "eint", "tdust", "eir")
 INPUTS = ("nh", "n_euv", "n_fuv", "zmet")
 OUT_F = ("y_h", "y_hp", "y_hm", "tgas")
+PHOTON_OUT = ("n_euv_out", "n_fuv_out")
 OUT_I = ("nsub", "niter", "flags")
 
 
-def to_device(cells: dict, device="cuda", outputs=True) -> dict:
+def to_device(cells: dict, device="cuda", outputs=True, photons=False) -> dict:
     """Copy a dict of host arrays (numpy or torch) to contiguous device
-    tensors and allocate the optional outputs."""
+    tensors and allocate the optional outputs (with photons, also the photon
+    densities after absorption)."""
     import torch
     out = {}
     n = None
@@ -174,6 +180,9 @@ def to_device(cells: dict, device="cuda", outputs=True) -> dict:
         out["nsub"] = torch.zeros(n, dtype=torch.int32, device=device)
         out["niter"] = torch.zeros(n, dtype=torch.int32, device=device)
         out["flags"] = torch.zeros(n, dtype=torch.int32, device=device)
+        if photons:
+            for k in PHOTON_OUT:
+                out[k] = torch.empty(n, dtype=torch.float64, device=device)
     return out
 
 
@@ -189,7 +198,7 @@ def make_cells(t: dict) -> SfcCells:
         raise ValueError("no cell arrays")
     c = SfcCells()
     c.n = n
-    for k in STATE + INPUTS + OUT_F:
+    for k in STATE + INPUTS + OUT_F + PHOTON_OUT:
         v = t.get(k)
         if v is not None:
             if v.dtype != torch.float64 or not v.is_cuda or not v.is_contiguous() or v.shape != (n,):

@@ -3,10 +3,18 @@
 Every HIP translation unit is compiled with packed FP32 instructions
 disabled (-target-feature -packed-fp32-ops); the host pass reports that it
 does not know the feature, which is expected.
+
+The build fails if a kernel spills vector registers to scratch memory.  A
+reload from scratch under a partial execution mask restores only the active
+lanes; the per-lane cell loops here diverge heavily, and a spilled kernel
+has been seen to return results that depended on which other cells shared
+its wavefront.  Spills of scalar registers (into vector register lanes)
+are allowed.
 """
 from __future__ import annotations
 
 import os
+import re
 import subprocess
 import sys
 
@@ -31,6 +39,21 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
          "-I" + INCLUDE, "-I" + CSRC]
 
 
+def vgpr_spills(remarks: str) -> dict:
+    """Kernels with a non-zero 'VGPRs Spill' in hipcc's resource-usage
+    remarks, with the count."""
+    out, name = {}, None
+    for ln in remarks.splitlines():
+        m = re.search(r"remark: Function Name: (\S+)", ln)
+        if m:
+            name = m.group(1)
+            continue
+        m = re.search(r"remark:\s+VGPRs Spill: (\d+)", ln)
+        if m and name and int(m.group(1)) > 0:
+            out[name] = int(m.group(1))
+    return out
+
+
 def build(verbose: bool = False) -> str:
     """Compile all sources and link libsfchem.so; returns the library path."""
     os.makedirs(BUILD, exist_ok=True)
@@ -39,10 +62,19 @@ def build(verbose: bool = False) -> str:
         path = os.path.join(CSRC, src)
         obj = os.path.join(BUILD, src + ".o")
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmd = ["hipcc", *FLAGS, *EXTRA.get(src, []), *lang, "-c", path, "-o", obj]
+        cmd = ["hipcc", *FLAGS, *EXTRA.get(src, []), *lang,
+               "-Rpass-analysis=kernel-resource-usage", "-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), file=sys.stderr)
-        subprocess.check_call(cmd)
+        r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+        other = [ln for ln in r.stdout.splitlines() if "kernel-resource-usage" not in ln]
+        if other and (verbose or r.returncode != 0):
+            print("\n".join(other), file=sys.stderr)
+        if r.returncode != 0:
+            raise subprocess.CalledProcessError(r.returncode, cmd)
+        spilled = vgpr_spills(r.stdout)
+        if spilled:
+            raise RuntimeError(f"{src}: kernels spill vector registers: {spilled}")
         objs.append(obj)
     tmp = LIB + ".tmp"
     cmd = ["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]

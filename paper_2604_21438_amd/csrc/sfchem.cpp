@@ -62,16 +62,23 @@ bool fill_net(const sfc_network& in, sfk::Net& o) {
     o.l_qe[j] = in.line_qe100[j];
     if (!(in.line_a[j] > 0.0)) return false;
   }
+  if ((in.pe_mode != 0 && in.pe_mode != 1) || (in.shield_mode != 0 && in.shield_mode != 1))
+    return false;
+  if (in.shield_mode == 1 && (!(in.shield_len > 0.0) || !(in.shield_b5 > 0.0))) return false;
+  o.sh_b5 = in.shield_b5;
+  o.pe_mode = in.pe_mode;
+  o.shield_mode = in.shield_mode;
   return true;
 }
 
 bool fill_par(const sfc_params& p, double z_default, double cd, const sfk::Net& net,
-              sfk::Par& o) {
+              double shield_len, sfk::Par& o) {
   if (!(p.f_chem > 0.0) || !(p.y_abs > 0.0) || !(p.newton_rtol > 0.0) || !(p.c_red > 0.0) ||
       !(p.t_cmb > 0.0) || !(p.y_he >= 0.0) || !(p.gamma_ad > 1.0) || p.n_cyc < 0 ||
       p.n_sub_max < 2 || p.newton_max < 1 || (p.ir_mode != 0 && p.ir_mode != 1) ||
       (p.thermal_mode != 0 && p.thermal_mode != 1) || (p.dust_mode != 0 && p.dust_mode != 1) ||
-      !(z_default >= 0.0) || !(cd > 0.0))
+      !(z_default >= 0.0) || !(cd > 0.0) || (p.photon_absorb != 0 && p.photon_absorb != 1) ||
+      p.reserved != 0)
     return false;
   o.f_chem = p.f_chem;
   o.y_abs = p.y_abs;
@@ -89,6 +96,11 @@ bool fill_par(const sfc_params& p, double z_default, double cd, const sfk::Net& 
   o.ir_mode = p.ir_mode;
   o.thermal_mode = p.thermal_mode;
   o.dust_mode = p.dust_mode;
+  o.photon_absorb = p.photon_absorb;
+  // x = N_H2 / 5e14 = y_H2 n_H shield_len sqrt(pi k_B T / (G m_H rho)) / 5e14
+  //   = y_H2 sh_k sqrt(n_H T), rho = (1 + 4 y_He) m_H n_H
+  constexpr double kGrav = 6.6743e-8, kMH = 1.67262192e-24, kPi = 3.14159265358979323846;
+  o.sh_k = shield_len * std::sqrt(kPi * KB / (kGrav * kMH * kMH * (1.0 + 4.0 * p.y_he))) / 5.0e14;
   // bound of k_H2/k_H3 over [1, 1e8] K (fine log grid, 5 % margin)
   double mx = 0.0;
   for (int i = 0; i <= 8000; ++i) {
@@ -100,6 +112,8 @@ bool fill_par(const sfc_params& p, double z_default, double cd, const sfk::Net& 
   o.hm_ratio_max = net.rm[3] > 0.0 ? 1.05 * mx * scale : 0.0;
   return true;
 }
+
+constexpr size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
 
@@ -174,6 +188,7 @@ sfk::Cells to_kcells(const sfc_cells* c) {
   k.y_h = c->y_h; k.y_hp = c->y_hp; k.y_hm = c->y_hm; k.tgas = c->tgas;
   k.nh = c->nh; k.n_euv = c->n_euv; k.n_fuv = c->n_fuv; k.zmet = c->zmet;
   k.nsub = c->nsub; k.niter = c->niter; k.flags = c->flags;
+  k.n_euv_out = c->n_euv_out; k.n_fuv_out = c->n_fuv_out;
   return k;
 }
 
@@ -219,6 +234,10 @@ void sfc_network_default(sfc_network* net) {
     net->line_qn[j] = qn[j];
     net->line_qe100[j] = qe[j];
   }
+  net->shield_len = 0.5;
+  net->shield_b5 = 2.0;
+  net->pe_mode = 0;
+  net->shield_mode = 0;
 }
 
 void sfc_params_default(sfc_params* p) {
@@ -259,7 +278,8 @@ int sfc_chem_init(const sfc_network* net_in, double z_default, double dust_cap_f
   if (!(dust_cap_factor > 0.0) || !std::isfinite(dust_cap_factor)) return SFC_E_INVAL;
   sfk::Net knet;
   sfk::Par kpar;
-  if (!fill_net(net, knet) || !fill_par(p, z_default, dust_cap_factor * 1.0e4, knet, kpar))
+  if (!fill_net(net, knet) ||
+      !fill_par(p, z_default, dust_cap_factor * 1.0e4, knet, net.shield_len, kpar))
     return SFC_E_INVAL;
   if (p.dispatch != SFC_DISPATCH_INDEX && p.dispatch != SFC_DISPATCH_DENSITY &&
       p.dispatch != SFC_DISPATCH_PROGRESS)
@@ -330,58 +350,77 @@ int sfc_chem_init(const sfc_network* net_in, double z_default, double dust_cap_f
 
 namespace {
 
-// Order buffer (cell order, bucket counters) of density and progress
-// dispatch, grown to n cells.
-bool ensure_order(sfc_ctx* ctx, int64_t n) {
-  if (n > ctx->order_cap) {
-    if (ctx->d_order) (void)hipFree(ctx->d_order);
-    ctx->d_order = nullptr;
-    ctx->order_cap = 0;
-    if (hipMalloc(&ctx->d_order, size_t(n) * sizeof(int32_t)) != hipSuccess) return false;
-    ctx->order_cap = n;
-  }
-  if (!ctx->d_buckets &&
-      hipMalloc(&ctx->d_buckets, sfk::kOrderWork * sizeof(uint32_t)) != hipSuccess)
-    return false;
-  return true;
-}
+// Dispatch buffers of one plain-path call: work counter, density / progress
+// order with its bucket counters, and the suspended-cell slots.
+struct StepBuffers {
+  unsigned long long* counter = nullptr;
+  int32_t* order = nullptr;
+  uint32_t* buckets = nullptr;
+  sfk::Suspended sus{};
+  int64_t sus_cap = 0;
+};
 
-// Suspended-cell slots of progress dispatch, one device block grown to n
-// slots: the slot counter, then rem, tiso (binary64), cell, nsub, nit,
-// flags, bucket (32-bit), each array 256-byte aligned.
-bool ensure_suspended(sfc_ctx* ctx, int64_t n, sfk::Suspended& sus) {
-  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-  if (n > ctx->sus_cap) {
-    if (ctx->d_sus) (void)hipFree(ctx->d_sus);
-    ctx->d_sus = nullptr;
-    ctx->sus_cap = 0;
-    const size_t bytes = 256 + 2 * al(size_t(n) * 8) + 5 * al(size_t(n) * 4);
-    if (hipMalloc(&ctx->d_sus, bytes) != hipSuccess) return false;
-    ctx->sus_cap = n;
-  }
-  const size_t cap = size_t(ctx->sus_cap);
-  char* b = static_cast<char*>(ctx->d_sus);
+// Slot arrays of progress dispatch carved from one block of n slots: the
+// slot counter, then rem, tiso (binary64), cell, nsub, nit, flags, bucket
+// (32-bit), each array 256-byte aligned.
+sfk::Suspended carve_suspended(void* base, int64_t n) {
+  sfk::Suspended sus;
+  char* b = static_cast<char*>(base);
+  const size_t cap = size_t(n);
   sus.count = reinterpret_cast<unsigned long long*>(b);
   b += 256;
   sus.rem = reinterpret_cast<double*>(b);
-  b += al(cap * 8);
+  b += al256(cap * 8);
   sus.tiso = reinterpret_cast<double*>(b);
-  b += al(cap * 8);
+  b += al256(cap * 8);
   sus.cell = reinterpret_cast<int32_t*>(b);
-  b += al(cap * 4);
+  b += al256(cap * 4);
   sus.nsub = reinterpret_cast<int32_t*>(b);
-  b += al(cap * 4);
+  b += al256(cap * 4);
   sus.nit = reinterpret_cast<int32_t*>(b);
-  b += al(cap * 4);
+  b += al256(cap * 4);
   sus.fl = reinterpret_cast<uint32_t*>(b);
-  b += al(cap * 4);
+  b += al256(cap * 4);
   sus.bucket = reinterpret_cast<int32_t*>(b);
+  return sus;
+}
+
+// The context's own buffers, grown (hipMalloc) to n cells.
+bool context_buffers(sfc_ctx* ctx, int64_t n, bool order, bool suspended, StepBuffers& b) {
+  b.counter = ctx->d_counter;
+  if (order) {
+    if (n > ctx->order_cap) {
+      if (ctx->d_order) (void)hipFree(ctx->d_order);
+      ctx->d_order = nullptr;
+      ctx->order_cap = 0;
+      if (hipMalloc(&ctx->d_order, size_t(n) * sizeof(int32_t)) != hipSuccess) return false;
+      ctx->order_cap = n;
+    }
+    if (!ctx->d_buckets &&
+        hipMalloc(&ctx->d_buckets, sfk::kOrderWork * sizeof(uint32_t)) != hipSuccess)
+      return false;
+    b.order = ctx->d_order;
+    b.buckets = ctx->d_buckets;
+  }
+  if (suspended) {
+    if (n > ctx->sus_cap) {
+      if (ctx->d_sus) (void)hipFree(ctx->d_sus);
+      ctx->d_sus = nullptr;
+      ctx->sus_cap = 0;
+      const size_t bytes = 256 + 2 * al256(size_t(n) * 8) + 5 * al256(size_t(n) * 4);
+      if (hipMalloc(&ctx->d_sus, bytes) != hipSuccess) return false;
+      ctx->sus_cap = n;
+    }
+    b.sus = carve_suspended(ctx->d_sus, ctx->sus_cap);
+    b.sus_cap = ctx->sus_cap;
+  }
   return true;
 }
 
 // Plain path launch; method 0 = LI binary64, 1 = LI mixed, 2 = NR binary64.
+// fixed: dispatch buffers to use (no allocation), else the context's own.
 int step_launch(sfc_ctx* ctx, const sfc_cells* cells, double dt, int method, void* hip_stream,
-                const char* who) {
+                const char* who, const StepBuffers* fixed = nullptr) {
   if (!ctx) return SFC_E_INVAL;
   if (!cells_ok(ctx->par, cells))
     return fail(ctx, SFC_E_INVAL, std::string(who) + ": bad cell buffers");
@@ -395,7 +434,6 @@ int step_launch(sfc_ctx* ctx, const sfc_cells* cells, double dt, int method, voi
   a.par = ctx->par;
   a.c = to_kcells(cells);
   a.dt = dt;
-  a.counter = ctx->d_counter;
   a.refill_min = ctx->refill_min;
   a.netc = ctx->d_net;
   a.parc = ctx->d_par;
@@ -414,42 +452,46 @@ int step_launch(sfc_ctx* ctx, const sfc_cells* cells, double dt, int method, voi
   // density order pays off once lanes take several cells each
   const bool density = ctx->dispatch != SFC_DISPATCH_INDEX && small_ids &&
                        cells->n > 2 * int64_t(grid) * sfk::kBlock;
-  if ((density || progress) && !ensure_order(ctx, cells->n))
-    return fail(ctx, SFC_E_NOMEM, std::string(who) + ": dispatch order buffer");
+  StepBuffers buf;
+  if (fixed) {
+    buf = *fixed;
+  } else if (!context_buffers(ctx, cells->n, density || progress, progress, buf)) {
+    return fail(ctx, SFC_E_NOMEM, std::string(who) + ": dispatch buffers");
+  }
+  a.counter = buf.counter;
   if (density) {
     // the first pass of progress dispatch orders every cell by density
     // (cells of one density share a wave and branch alike); plain density
     // dispatch orders the densest quarter and keeps the rest in index order
-    const hipError_t oe = sfk::launch_order(cells->nh, cells->n, progress, ctx->d_order,
-                                            ctx->d_buckets, s);
+    const hipError_t oe = sfk::launch_order(cells->nh, cells->n, progress, buf.order,
+                                            buf.buckets, s);
     if (oe != hipSuccess) return hip_fail(ctx, oe, "dispatch order launch");
-    a.order = ctx->d_order;
-    a.dense = ctx->d_buckets + sfk::kOrderDenseWord;
+    a.order = buf.order;
+    a.dense = buf.buckets + sfk::kOrderDenseWord;
   }
   if (progress) {
-    if (!ensure_suspended(ctx, cells->n, a.sus))
-      return fail(ctx, SFC_E_NOMEM, std::string(who) + ": suspended-cell slots");
+    a.sus = buf.sus;
     a.budget = ctx->phase_nsub;
     const hipError_t re = sfk::launch_reset(a.sus.count, s);
     if (re != hipSuccess) return hip_fail(ctx, re, "reset launch");
   }
-  hipError_t e = sfk::launch_reset(ctx->d_counter, s);
+  hipError_t e = sfk::launch_reset(buf.counter, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "reset launch");
   e = method == 2 ? sfk::launch_step_nr(a, grid, s) : sfk::launch_step(a, method, grid, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "step launch");
   if (progress) {
     // second pass: the suspended cells, longest estimated remainder first
-    e = sfk::launch_progress_order(a.sus, dt, ctx->par.n_sub_max, ctx->sus_cap, ctx->d_buckets,
-                                   ctx->d_order, s);
+    e = sfk::launch_progress_order(a.sus, dt, ctx->par.n_sub_max, buf.sus_cap, buf.buckets,
+                                   buf.order, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "progress order launch");
     sfk::Args b = a;
     b.budget = 0;
     b.resume = 1;
     b.fine = 1;
-    b.order = ctx->d_order;
+    b.order = buf.order;
     b.dense = nullptr;
     b.limit = a.sus.count;
-    e = sfk::launch_reset(ctx->d_counter, s);
+    e = sfk::launch_reset(buf.counter, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "reset launch");
     e = sfk::launch_step(b, method, grid, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "step launch");
@@ -471,6 +513,7 @@ int sfc_chem_step(sfc_ctx* ctx, const sfc_cells* cells, double dt, int precision
 int sfc_chem_step_nr(sfc_ctx* ctx, const sfc_cells* cells, double dt, void* hip_stream) {
   return step_launch(ctx, cells, dt, 2, hip_stream, "sfc_chem_step_nr");
 }
+
 
 int sfc_chem_submit(sfc_ctx* ctx, const sfc_request* req, uint64_t* ticket) {
   if (!ctx || !req || !ticket) return SFC_E_INVAL;

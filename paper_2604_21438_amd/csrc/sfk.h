@@ -28,6 +28,9 @@ struct Net {
   double e_fuv, e_euv;  // photon energies [erg]
   double x_c, x_o, f_oiii;
   double l_tul[5], l_a[5], l_g[5], l_qn[5], l_qe[5];
+  double sh_b5;         // Doppler parameter of the H2 self-shielding fit [km/s]
+  int32_t pe_mode;      // 0 constant photoelectric efficiency, 1 grain charging
+  int32_t shield_mode;  // 0 no H2 self-shielding, 1 local H2 column
 };
 
 struct Par {
@@ -36,7 +39,9 @@ struct Par {
   double cd;             // C_d [erg/g/K]
   double z_default;
   double hm_ratio_max;   // upper bound of y_H-/y_e = k_H2/k_H3 over the rate range
+  double sh_k;           // H2 column / 5e14 cm^-2 = y_H2 sh_k sqrt(n_H T) (self-shielding)
   int32_t n_cyc, n_sub_max, newton_max, ir_mode, thermal_mode, dust_mode;
+  int32_t photon_absorb; // 1: attenuated photon densities written after the step
 };
 
 struct Cells {
@@ -46,6 +51,7 @@ struct Cells {
   const double *nh, *n_euv, *n_fuv, *zmet;
   int32_t *nsub, *niter;
   uint32_t *flags;
+  double *n_euv_out, *n_fuv_out;  // photon densities after absorption (optional)
 };
 
 // Cells suspended by the first pass of two-phase dispatch, one slot each

@@ -312,43 +312,97 @@ struct Mth<float> {
   __device__ static float dv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 };
 
-// value with partials w.r.t. (y_H2, y_e, T)
-template <class R>
-struct G {
+// Value with partials w.r.t. (y_H2, y_e, T).  The mask M says which
+// partials can be non-zero (kDA: d/dy_H2, kDE: d/dy_e, kDT: d/dT); the
+// others are exactly zero by construction (y_H2 does not depend on y_e,
+// a rate coefficient depends on T only, ...).  The operators compute only
+// the partials in the result's mask, so the structural zeros are neither
+// multiplied nor added: IEEE arithmetic does not let the compiler drop
+// x * 0 or x + 0 * y on its own.  Absent partials hold an exact 0.
+constexpr unsigned kDA = 1u, kDE = 2u, kDT = 4u, kDAll = 7u;
+template <class R, unsigned M>
+struct D {
   R v, a, e, t;
 };
+template <class R>
+using G = D<R, kDAll>;  // all partials
+template <class R, unsigned M>
+__device__ inline G<R> dense(D<R, M> x) {
+  return {x.v, x.a, x.e, x.t};
+}
 // function of T only
 template <class R>
 struct TF {
   R v, t;
 };
 
-template <class R>
-__device__ inline G<R> operator+(G<R> x, G<R> y) {
-  return {x.v + y.v, x.a + y.a, x.e + y.e, x.t + y.t};
+template <unsigned B, unsigned M1, unsigned M2, class R>
+__device__ inline R p_add(R x, R y) {
+  if constexpr ((M1 & B) && (M2 & B)) return x + y;
+  else if constexpr ((M1 & B) != 0) return x;
+  else if constexpr ((M2 & B) != 0) return y;
+  else return R(0);
 }
-template <class R>
-__device__ inline G<R> operator-(G<R> x, G<R> y) {
-  return {x.v - y.v, x.a - y.a, x.e - y.e, x.t - y.t};
+template <unsigned B, unsigned M1, unsigned M2, class R>
+__device__ inline R p_sub(R x, R y) {
+  if constexpr ((M1 & B) && (M2 & B)) return x - y;
+  else if constexpr ((M1 & B) != 0) return x;
+  else if constexpr ((M2 & B) != 0) return -y;
+  else return R(0);
 }
-template <class R>
-__device__ inline G<R> operator*(G<R> x, G<R> y) {
-  return {x.v * y.v, x.a * y.v + x.v * y.a, x.e * y.v + x.v * y.e, x.t * y.v + x.v * y.t};
+// partial of a product: x' y + x y'
+template <unsigned B, unsigned M1, unsigned M2, class R>
+__device__ inline R p_mul(R xp, R yv, R xv, R yp) {
+  if constexpr ((M1 & B) && (M2 & B)) return xp * yv + xv * yp;
+  else if constexpr ((M1 & B) != 0) return xp * yv;
+  else if constexpr ((M2 & B) != 0) return xv * yp;
+  else return R(0);
 }
-template <class R>
-__device__ inline G<R> operator*(R s, G<R> x) {
-  return {s * x.v, s * x.a, s * x.e, s * x.t};
+template <unsigned B, unsigned M, class R>
+__device__ inline R p_scale(R s, R xp) {
+  if constexpr ((M & B) != 0) return s * xp;
+  else return R(0);
 }
-template <class R>
-__device__ inline G<R> operator*(TF<R> k, G<R> x) {
-  return {k.v * x.v, k.v * x.a, k.v * x.e, k.t * x.v + k.v * x.t};
+
+template <class R, unsigned M1, unsigned M2>
+__device__ inline D<R, M1 | M2> operator+(D<R, M1> x, D<R, M2> y) {
+  return {x.v + y.v, p_add<kDA, M1, M2>(x.a, y.a), p_add<kDE, M1, M2>(x.e, y.e),
+          p_add<kDT, M1, M2>(x.t, y.t)};
 }
-template <class R>
-__device__ inline G<R> quot(G<R> x, G<R> y) {
-  using M = Mth<R>;
-  R iy = M::dv(R(1), y.v);
-  R q = x.v * iy;
-  return {q, (x.a - q * y.a) * iy, (x.e - q * y.e) * iy, (x.t - q * y.t) * iy};
+template <class R, unsigned M1, unsigned M2>
+__device__ inline D<R, M1 | M2> operator-(D<R, M1> x, D<R, M2> y) {
+  return {x.v - y.v, p_sub<kDA, M1, M2>(x.a, y.a), p_sub<kDE, M1, M2>(x.e, y.e),
+          p_sub<kDT, M1, M2>(x.t, y.t)};
+}
+template <class R, unsigned M1, unsigned M2>
+__device__ inline D<R, M1 | M2> operator*(D<R, M1> x, D<R, M2> y) {
+  return {x.v * y.v, p_mul<kDA, M1, M2>(x.a, y.v, x.v, y.a),
+          p_mul<kDE, M1, M2>(x.e, y.v, x.v, y.e), p_mul<kDT, M1, M2>(x.t, y.v, x.v, y.t)};
+}
+template <class R, unsigned M>
+__device__ inline D<R, M> operator*(R s, D<R, M> x) {
+  return {s * x.v, p_scale<kDA, M>(s, x.a), p_scale<kDE, M>(s, x.e), p_scale<kDT, M>(s, x.t)};
+}
+template <class R, unsigned M>
+__device__ inline D<R, M | kDT> operator*(TF<R> k, D<R, M> x) {
+  return {k.v * x.v, p_scale<kDA, M>(k.v, x.a), p_scale<kDE, M>(k.v, x.e),
+          p_mul<kDT, kDT, M>(k.t, x.v, k.v, x.t)};
+}
+// quotient: partials (x' - q y') / y
+template <unsigned B, unsigned M1, unsigned M2, class R>
+__device__ inline R p_quot(R xp, R q, R yp, R iy) {
+  if constexpr ((M1 & B) && (M2 & B)) return (xp - q * yp) * iy;
+  else if constexpr ((M1 & B) != 0) return xp * iy;
+  else if constexpr ((M2 & B) != 0) return -(q * yp) * iy;
+  else return R(0);
+}
+template <class R, unsigned M1, unsigned M2>
+__device__ inline D<R, M1 | M2> quot(D<R, M1> x, D<R, M2> y) {
+  using Mt = Mth<R>;
+  const R iy = Mt::dv(R(1), y.v);
+  const R q = x.v * iy;
+  return {q, p_quot<kDA, M1, M2>(x.a, q, y.a, iy), p_quot<kDE, M1, M2>(x.e, q, y.e, iy),
+          p_quot<kDT, M1, M2>(x.t, q, y.t, iy)};
 }
 
 // ------------------------------------------------------------------ rates
@@ -409,28 +463,31 @@ struct Acc {
 struct CellK {
   double n, fd, rho;
   double k9, k10, k11;  // photo / CR rates
-  double g4;            // photoelectric heating / (k_B n) [K/s]
+  double g4;            // photoelectric heating / (k_B n) [K/s] (pe_mode 0), G0 (pe_mode 1)
   double euv;           // dust UV absorption [erg/g/s]
 };
 
-// A += s * (k * x), k a function of T only
-template <class R>
-__device__ inline void acc(G<R>& A, R s, TF<R> k, G<R> x) {
+// A += s * (k * x), k a function of T only; the accumulator's mask holds x's
+template <class R, unsigned MA, unsigned M>
+__device__ inline void acc(D<R, MA>& A, R s, TF<R> k, D<R, M> x) {
+  static_assert((M | kDT | MA) == MA, "accumulator lacks a partial of the term");
   const R kv = s * k.v, kt = s * k.t;
   A.v = A.v + kv * x.v;
-  A.a = A.a + kv * x.a;
-  A.e = A.e + kv * x.e;
-  A.t = A.t + (kt * x.v + kv * x.t);
+  if constexpr ((M & kDA) != 0) A.a = A.a + kv * x.a;
+  if constexpr ((M & kDE) != 0) A.e = A.e + kv * x.e;
+  if constexpr ((M & kDT) != 0) A.t = A.t + (kt * x.v + kv * x.t);
+  else A.t = A.t + kt * x.v;
 }
 // the same into a net-source accumulator: each term rounded in R, the sum
 // in binary64 (for R = double the arithmetic of the overload above)
-template <class R>
-__device__ inline void acc(Acc<R>& A, R s, TF<R> k, G<R> x) {
+template <class R, unsigned M>
+__device__ inline void acc(Acc<R>& A, R s, TF<R> k, D<R, M> x) {
   const R kv = s * k.v, kt = s * k.t;
   A.v = A.v + double(kv) * double(x.v);
-  A.a = A.a + kv * x.a;
-  A.e = A.e + kv * x.e;
-  A.t = A.t + (kt * x.v + kv * x.t);
+  if constexpr ((M & kDA) != 0) A.a = A.a + kv * x.a;
+  if constexpr ((M & kDE) != 0) A.e = A.e + kv * x.e;
+  if constexpr ((M & kDT) != 0) A.t = A.t + (kt * x.v + kv * x.t);
+  else A.t = A.t + kt * x.v;
 }
 
 // Chemistry and gas heating/cooling with partials; T_d frozen.  Each rate
@@ -477,12 +534,12 @@ __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, d
   const double yhp_d = yed + yhm_d;
   const double yh_d = 1.0 - 2.0 * y2d - yhp_d - yhm_d;
   const R ye = R(yed);
-  const G<R> Y2{R(y2d), R(1), R(0), R(0)};
-  const G<R> YE{ye, R(0), R(1), R(0)};
-  const G<R> YHM{R(yhm_d), R(0), ratio, dratio * ye};
-  const G<R> YHP{R(yhp_d), R(0), R(1) + ratio, dratio * ye};
+  const D<R, kDA> Y2{R(y2d), R(1), R(0), R(0)};
+  const D<R, kDE> YE{ye, R(0), R(1), R(0)};
+  const D<R, kDE | kDT> YHM{R(yhm_d), R(0), ratio, dratio * ye};
+  const D<R, kDE | kDT> YHP{R(yhp_d), R(0), R(1) + ratio, dratio * ye};
   const G<R> YH{R(yh_d), R(-2), R(-1) - R(2) * ratio, R(-2) * dratio * ye};
-  const G<R> HE = YH * YE;
+  const auto HE = YH * YE;
 
   Acc<R> rh2{0.0, R(0), R(0), R(0)}, re = rh2, q = rh2;
   const R evn = R(EVK) * n;  // eV / k_B * n_H
@@ -538,8 +595,8 @@ __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, d
     const TF<R> k3m{k3.v * R(nt.rm[3]), k3.t * R(nt.rm[3])};
     acc(q, g1 * R(3.73), k3m, f * (YH * YHM));
   }
-  const G<R> H2H = Y2 * YH;
-  const G<R> H22 = Y2 * Y2;
+  const auto H2H = Y2 * YH;
+  const auto H22 = Y2 * Y2;
   // H4 collisional dissociation by H (stand-in rate) and Lambda_6 (part)
   {
     TF<R> k4;
@@ -554,8 +611,8 @@ __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, d
     const R t25 = M::sq(rsT);
     const TF<R> k5{R(6.0e-32) * t25 + R(2.0e-31) * t50,
                    (R(-0.25 * 6.0e-32) * t25 - R(0.5 * 2.0e-31) * t50) * iT};
-    const G<R> HH = YH * YH;
-    const G<R> HHH = HH * YH;
+    const auto HH = YH * YH;
+    const auto HHH = HH * YH;
     acc(rh2, R(nt.rm[5]) * n * n, k5, HHH);
     acc(rh2, R(nt.rm[6] * 0.125) * n * n, k5, HH * Y2);
     acc(q, g1 * R(4.48) * n * R(nt.rm[5]), k5, f * HHH);
@@ -600,10 +657,61 @@ __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, d
   {
     const R k9 = R(ck.k9), k10 = R(ck.k10), k11 = R(ck.k11);
     acc(re, k9 + k11, TF<R>{R(1), R(0)}, YH);
-    acc(rh2, -k10, TF<R>{R(1), R(0)}, Y2);
     acc(q, R(nt.pm[1] * nt.g2k) * k9, TF<R>{R(1), R(0)}, YH);
-    acc(q, R(nt.pm[2] * nt.g3k) * k10, TF<R>{R(1), R(0)}, Y2);
-    q.v = q.v + ck.g4;
+    if (nt.shield_mode == 1) {
+      // H2 self-shielding (stand-in, the fit of Draine & Bertoldi 1996):
+      // f = 0.965 / (1 + x/b5)^2 + 0.035 / s exp(-8.5e-4 s), s = sqrt(1 + x),
+      // x = y_H2 sh_k sqrt(n_H T) (local column of shield_len Jeans lengths)
+      const double xk = pr.sh_k * fsqrt(ck.n * T64);  // dx / dy_H2
+      const double x = y2d * xk;
+      const R iu = M::dv(R(1), R(1) + R(x / nt.sh_b5));
+      const R sq = M::sq(R(1) + R(x));
+      const R isq = M::dv(R(1), sq);
+      const R ex = M::ea(-8.5e-4 * double(sq));
+      const R f = R(0.965) * iu * iu + R(0.035) * isq * ex;
+      const R dfdx = R(-2.0 * 0.965 / nt.sh_b5) * iu * iu * iu +
+                     R(0.5 * 0.035) * ex * isq * (-(isq * isq) - R(8.5e-4) * isq);
+      const D<R, kDA | kDT> fsh{f, dfdx * R(xk), R(0), dfdx * R(x) * R(0.5) * iT};
+      const auto S2 = fsh * Y2;
+      acc(rh2, -k10, TF<R>{R(1), R(0)}, S2);
+      acc(q, R(nt.pm[2] * nt.g3k) * k10, TF<R>{R(1), R(0)}, S2);
+    } else {
+      acc(rh2, -k10, TF<R>{R(1), R(0)}, Y2);
+      acc(q, R(nt.pm[2] * nt.g3k) * k10, TF<R>{R(1), R(0)}, Y2);
+    }
+    if (nt.pe_mode != 1) {
+      q.v = q.v + ck.g4;
+    } else if (ck.g4 > 0.0) {
+      // photoelectric heating with grain charging and the cooling by
+      // electron recombination on grains (stand-in: Bakes & Tielens 1994 in
+      // the form of Wolfire et al. 2003), psi = G0 sqrt(T) / n_e with n_e
+      // floored at y_abs n_H; per k_B n_H
+      const bool floored = yed < pr.y_abs;
+      const double lnpsi = flog(ck.g4) + 0.5 * lnT64 - flog((floored ? pr.y_abs : yed) * ck.n);
+      const R psi = M::ea(lnpsi);
+      const R ipsi = M::ea(-lnpsi);
+      const R dpsi_e = floored ? R(0) : -psi * M::dv(R(1), ye);  // d psi / d y_e
+      const R dpsi_t = R(0.5) * psi * iT;
+      const R p73 = M::ea(0.73 * lnpsi);
+      const R ia = M::dv(R(1), R(1) + R(4e-3) * p73);
+      const R tt = M::ea(0.7 * (lnT64 - 9.210340371976184));  // (T / 1e4)^0.7
+      const R ib = M::dv(R(1), R(1) + R(2e-4) * psi);
+      const R eps = R(0.0487) * ia + R(0.0365) * tt * ib;
+      const R deps = R(-0.0487 * 4e-3 * 0.73) * p73 * ipsi * ia * ia -
+                     R(0.0365 * 2e-4) * tt * ib * ib;  // d eps / d psi
+      const R deps_t = R(0.0365 * 0.7) * tt * iT * ib;
+      const R ch = R(nt.pm[3] * 1.3e-24 / KB * ck.g4 * ck.fd);
+      const R beta = R(0.735) * M::ea(-0.068 * lnT64);
+      const R pb = M::ea(double(beta) * lnpsi);
+      const R t94 = M::ea(0.94 * lnT64);
+      const R cr = R(nt.pm[3] * 4.65e-30 / KB * ck.n * ck.fd);
+      const R rec = cr * ye * t94 * pb;
+      const R rec_e = cr * t94 * pb * (floored ? R(1) : R(1) - beta);
+      const R rec_t = rec * (R(0.94) * iT - R(0.068) * beta * iT * R(lnpsi) + beta * R(0.5) * iT);
+      q.v = q.v + (double(ch * eps) - double(rec));
+      q.e = q.e + (ch * deps * dpsi_e - rec_e);
+      q.t = q.t + (ch * (deps * dpsi_t + deps_t) - rec_t);
+    }
   }
   // Lambda_7, recombination cooling fit in log10 T (10^P / k_B)
   {
@@ -653,9 +761,8 @@ __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, d
   // Lambda_13, line cooling: two-level coolants (stand-in)
   {
     const R s100 = R(10) * rsT;  // (100 / T)^1/2
-    G<R> ncoll = YH + Y2;
-    ncoll = n * ncoll;
-    G<R> nel{R(0), R(0), R(0), R(0)};
+    const G<R> ncoll = n * (YH + Y2);
+    D<R, kDE | kDT> nel{R(0), R(0), R(0), R(0)};
     acc(nel, n, TF<R>{s100, R(-0.5) * s100 * iT}, YE);
     const R xo = R(nt.x_o * ck.fd);
     const R m13 = -R(nt.pm[12]);
@@ -663,11 +770,11 @@ __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, d
 #pragma unroll 1
     for (int j = 0; j < 5; ++j) {
       G<R> emit;
-      if (j == 0) emit = Y2;
+      if (j == 0) emit = dense(Y2);
       else if (j == 1) emit = G<R>{R(nt.x_c * ck.fd), R(0), R(0), R(0)};
       else if (j == 2) emit = G<R>{xo * (R(1) - YHP.v), R(0), -xo * YHP.e, -xo * YHP.t};
-      else if (j == 3) emit = (xo * R(1.0 - nt.f_oiii)) * YHP;
-      else emit = (xo * R(nt.f_oiii)) * YHP;
+      else if (j == 3) emit = dense((xo * R(1.0 - nt.f_oiii)) * YHP);
+      else emit = dense((xo * R(nt.f_oiii)) * YHP);
       const double tul = nt.l_tul[j];
       const R b = M::ea(-tul * iT64);
       const G<R> cul = R(nt.l_qn[j]) * ncoll + R(nt.l_qe[j]) * nel;
@@ -1250,14 +1357,14 @@ __device__ inline bool nr_inner(const Net& nt, const Par& pr, const CellK& ck, c
 }
 
 // One backward-Euler substep of length dts from L; on success L holds the
-// new state.  Outer iterations are counted in L.nit.
-__device__ bool nr_substep(const Net& nt, const Par& pr, Lane& L, double dts) {
+// new state.  Outer iterations are counted in L.nit, inner ones in its.
+__device__ bool nr_substep_iter(const Net& nt, const Par& pr, Lane& L, double dts,
+                                int32_t& its) {
   const bool iso = pr.thermal_mode == 1;
   const bool dust_on = (pr.dust_mode == 0) && !iso;
   const double knb = KB * L.ck.n;
   const Lane s0 = L;
   NRState g{L.y2, L.ye, iso ? L.Tiso : L.E / (knb * cvk(pr, L.y2, L.ye)), L.Td, L.Eir};
-  int32_t its = 0;
   if (iso) {
     double Gv;
     if (!nr_inner(nt, pr, L.ck, s0, dts, L.Tiso, 1e-5, dust_on, g, Gv, its)) return false;
@@ -1306,6 +1413,16 @@ __device__ bool nr_substep(const Net& nt, const Par& pr, Lane& L, double dts) {
   return false;
 }
 
+// One substep; L.nit counts every Newton iteration of it: outer iterations
+// and the inner dust/IR and chemistry iterations (so two runs take the same
+// iteration path only if every convergence test came out the same).
+__device__ bool nr_substep(const Net& nt, const Par& pr, Lane& L, double dts) {
+  int32_t its = 0;
+  const bool ok = nr_substep_iter(nt, pr, L, dts, its);
+  L.nit += its;
+  return ok;
+}
+
 constexpr uint32_t F_NRFAIL = 32u;
 
 // One substep attempt of the NR driver (Eq. substep_NRchem): the first
@@ -1348,7 +1465,7 @@ __device__ inline void cell_consts(const Net& nt, const Par& pr, double nh, doub
   k.k9 = nt.rm[9] * (nt.c_sigma * ne);
   k.k10 = nt.rm[10] * (nt.k10g * g0);
   k.k11 = nt.rm[11] * nt.zeta;
-  k.g4 = nt.pm[3] * nt.pe_k * g0 * z;  // Gamma_4 / (k_B n)
+  k.g4 = nt.pe_mode == 1 ? g0 : nt.pm[3] * nt.pe_k * g0 * z;  // Gamma_4 / (k_B n), or G0
   k.euv = nt.kap_uv_c * (nf * nt.e_fuv + ne * nt.e_euv);
 }
 
@@ -1415,6 +1532,8 @@ __device__ bool load_cell(const Net& nt, const Par& pr, const Cells& c, int64_t 
     if (c.nsub) c.nsub[i] = 0;
     if (c.niter) c.niter[i] = 0;
     if (c.flags) c.flags[i] = F_INVALID;
+    if (c.n_euv_out) c.n_euv_out[i] = ne;  // an invalid cell absorbs nothing
+    if (c.n_fuv_out) c.n_fuv_out[i] = nf;
     return false;
   }
   cell_consts(nt, pr, nh, ne, nf, z, L.ck);
@@ -1429,7 +1548,7 @@ __device__ bool load_cell(const Net& nt, const Par& pr, const Cells& c, int64_t 
 
 template <class R>
 __device__ void store_cell(const Net& nt, const Par& pr, const Cells& c, int64_t i,
-                           const Lane& L) {
+                           const Lane& L, double dt = 0.0) {
   c.y_h2[i] = L.y2;
   c.y_e[i] = L.ye;
   c.eint[i] = L.E;
@@ -1437,13 +1556,24 @@ __device__ void store_cell(const Net& nt, const Par& pr, const Cells& c, int64_t
   if (pr.ir_mode == 1) c.eir[i] = L.Eir;
   const bool iso = pr.thermal_mode == 1;
   const double T = iso ? L.Tiso : L.E / (KB * L.ck.n * cvk(pr, L.y2, L.ye));
-  if (c.y_h || c.y_hp || c.y_hm) {
+  const bool absorb = pr.photon_absorb == 1 && (c.n_euv_out || c.n_fuv_out);
+  if (c.y_h || c.y_hp || c.y_hm || absorb) {
     const double r = hm_ratio<double>(nt, T);
     const double yhm = r * L.ye;
     const double yhp = L.ye + yhm;
-    if (c.y_h) c.y_h[i] = 1.0 - 2.0 * L.y2 - yhp - yhm;
+    const double yh = 1.0 - 2.0 * L.y2 - yhp - yhm;
+    if (c.y_h) c.y_h[i] = yh;
     if (c.y_hp) c.y_hp[i] = yhp;
     if (c.y_hm) c.y_hm[i] = yhm;
+    if (absorb) {
+      // photons absorbed over the step by the updated gas (Sec. 2
+      // "Radiation components"; stand-in): N exp(-c~ alpha dt) with
+      // c alpha_EUV = c sigma n_H y_H + c kappa_UV rho f_d, c alpha_FUV = c kappa_UV rho f_d
+      const double ad = nt.kap_uv_c * L.ck.rho * L.ck.fd;
+      const double ae = nt.c_sigma * L.ck.n * fmax(yh, 0.0) + ad;
+      if (c.n_euv_out) c.n_euv_out[i] = c.n_euv[i] * fexp(-(pr.c_red * ae * dt));
+      if (c.n_fuv_out) c.n_fuv_out[i] = c.n_fuv[i] * fexp(-(pr.c_red * ad * dt));
+    }
   }
   if (c.tgas) c.tgas[i] = T;
   if (c.nsub) c.nsub[i] = L.nsub;

@@ -21,11 +21,8 @@ constexpr unsigned kStash = 64;
 
 // kNR selects the Newton-Raphson comparator instead of the LI subcycle
 // (binary64 only); both share the lane refill, stash and dispatch.
-// At least two waves per SIMD for every instantiation: the NR comparator
-// would otherwise settle at one wave for a few registers over the limit.
 template <class R, bool kNR>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
-void li_step_kernel(Args) {
+__device__ __attribute__((always_inline)) inline void step_loop() {
   stage_tables();
   const int lane = threadIdx.x & 63;
   int64_t cell = -1;
@@ -86,7 +83,7 @@ void li_step_kernel(Args) {
       const bool done = kNR ? nr_attempt(fresh(a.netc), fresh(a.parc), L, tsub, lev, attempts)
                             : subcycle<R>(fresh(a.netc), fresh(a.parc), L);
       if (done) {
-        store_cell<R>(fresh(a.netc), fresh(a.parc), a.c, cell, L);
+        store_cell<R>(fresh(a.netc), fresh(a.parc), a.c, cell, L, a.dt);
         cell = -1;
       } else if (!kNR && a.budget > 0 && L.nsub >= a.budget) {
         // first pass over: one slot counter update per wave
@@ -101,6 +98,17 @@ void li_step_kernel(Args) {
     }
   }
 }
+
+// The LI kernels at two waves per SIMD (their register peak fits 256).
+template <class R>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
+void li_step_kernel(Args) { step_loop<R, false>(); }
+
+// The NR comparator holds three trial states and the Newton systems of its
+// nested loops at once: at two waves per SIMD it spilled ~50 registers to
+// scratch, so it runs at one wave per SIMD with every value in registers.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1)))
+void nr_step_kernel(Args) { step_loop<double, true>(); }
 
 __global__ void reset_kernel(unsigned long long* counter) { *counter = 0ull; }
 
@@ -335,14 +343,14 @@ __global__ __launch_bounds__(256) void progress_scatter_kernel(Suspended sus, ui
 
 hipError_t launch_step(const Args& a, int precision, int grid, hipStream_t s) {
   if (precision == 1)
-    hipLaunchKernelGGL((li_step_kernel<float, false>), dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((li_step_kernel<float>), dim3(grid), dim3(kBlock), 0, s, a);
   else
-    hipLaunchKernelGGL((li_step_kernel<double, false>), dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((li_step_kernel<double>), dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_step_nr(const Args& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((li_step_kernel<double, true>), dim3(grid), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL((nr_step_kernel), dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
@@ -354,13 +362,13 @@ hipError_t launch_reset(unsigned long long* counter, hipStream_t s) {
 int max_blocks_per_cu(int precision) {
   int nb = 0;
   if (precision == 2)
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, li_step_kernel<double, true>, kBlock,
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, nr_step_kernel, kBlock,
                                                        0);
   else if (precision == 1)
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, li_step_kernel<float, false>, kBlock,
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, li_step_kernel<float>, kBlock,
                                                        0);
   else
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, li_step_kernel<double, false>, kBlock,
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, li_step_kernel<double>, kBlock,
                                                        0);
   return nb > 0 ? nb : 1;
 }

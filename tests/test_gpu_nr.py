@@ -5,7 +5,9 @@ NR stops each loop at a relative tolerance (1e-5, 1e-3 after 10 outer
 iterations), so where binary64 rounding flips a convergence decision the
 result moves by up to that tolerance.  Bar: cells the reference determines
 to 1e-10 (rounding spread over six other valid roundings of the reference
-NR) and that take the same substeps and outer iterations match to 1e-9
+NR) and that take the same substeps and Newton iterations (niter counts
+outer, dust/IR and chemistry iterations, so equal counts mean every
+convergence test came out the same) match to 1e-9
 relative; other cells on the same path match to max(1e-9, 10 x spread);
 where the iteration path differs (a convergence test decided within
 rounding of its tolerance), to the NR tolerance 1e-3.  The number of cells
