@@ -233,6 +233,23 @@ int sfc_chem_step(sfc_ctx* ctx, const sfc_cells* cells, double dt_seconds, int p
  * Errors: SFC_E_INVAL, SFC_E_NOMEM, SFC_E_DEVICE. */
 int sfc_chem_step_nr(sfc_ctx* ctx, const sfc_cells* cells, double dt_seconds, void* hip_stream);
 
+/* sfc_chem_step for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, results (bitwise), asynchrony and errors as
+ * sfc_chem_step, but the call allocates nothing: the dispatch buffers of
+ * the call (work counter, cell order, suspended-cell slots; ~40 B per cell)
+ * live in a file-scope device array of the library, one per GPU (80 MiB,
+ * held until the process ends), so n is limited to SFC_NOALLOC_MAX_CELLS;
+ * larger n returns SFC_E_INVAL.  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (other streams, other contexts,
+ * other threads) race and must not be issued; calls in stream order are
+ * fine.  The array needs no clearing between calls (the call's kernels
+ * reset what they count with).  SFC_E_DEVICE if the array's device address
+ * could not be taken when the context was created. */
+#define SFC_NOALLOC_MAX_CELLS 2097152
+int sfc_chem_step_noalloc(sfc_ctx* ctx, const sfc_cells* cells, double dt_seconds,
+                          int precision, void* hip_stream);
+
 /* ---- served form: continuous batching of AMR blocks ---- */
 
 /* One request: a set of cells (typically whole 8^3 blocks) with its own dt

@@ -24,6 +24,7 @@ DUST_EVOLVE, DUST_FROZEN = 0, 1
 F_CAP, F_TIGHT, F_NOCONV, F_INVALID, F_FLOOR, F_NRFAIL = 1, 2, 4, 8, 16, 32
 OK, E_INVAL, E_NOMEM, E_BUDGET, E_DEVICE, E_PENDING, E_VERSION, E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
 ABI_VERSION = 4
+NOALLOC_MAX_CELLS = 2097152
 REQ_RESUME, REQ_WRITEBACK = 1, 2
 NREAC, NPROC, NLINE = 12, 14, 5
 
@@ -78,7 +79,7 @@ class SfcResult(C.Structure):
 
 
 EXPORTS = ("sfc_network_default", "sfc_params_default", "sfc_chem_init", "sfc_chem_step",
-           "sfc_chem_step_nr", "sfc_chem_submit", "sfc_chem_poll",
+           "sfc_chem_step_nr", "sfc_chem_step_noalloc", "sfc_chem_submit", "sfc_chem_poll",
            "sfc_chem_fetch",
            "sfc_chem_release", "sfc_chem_drain", "sfc_chem_destroy", "sfc_strerror",
            "sfc_last_error", "sfc_now")
@@ -106,6 +107,7 @@ def lib():
                                     P(C.c_void_p)]
         L.sfc_chem_step.argtypes = [C.c_void_p, P(SfcCells), _d, C.c_int, C.c_void_p]
         L.sfc_chem_step_nr.argtypes = [C.c_void_p, P(SfcCells), _d, C.c_void_p]
+        L.sfc_chem_step_noalloc.argtypes = [C.c_void_p, P(SfcCells), _d, C.c_int, C.c_void_p]
         L.sfc_chem_submit.argtypes = [C.c_void_p, P(SfcRequest), P(C.c_uint64)]
         L.sfc_chem_poll.argtypes = [C.c_void_p, C.c_uint64, P(SfcResult)]
         L.sfc_chem_fetch.argtypes = [C.c_void_p, C.c_uint64, P(SfcCells), C.c_void_p]
@@ -117,7 +119,8 @@ def lib():
         L.sfc_last_error.argtypes = [C.c_void_p]
         L.sfc_last_error.restype = C.c_char_p
         L.sfc_now.restype = _d
-        for name in ("sfc_chem_init", "sfc_chem_step", "sfc_chem_step_nr", "sfc_chem_submit",
+        for name in ("sfc_chem_init", "sfc_chem_step", "sfc_chem_step_nr", "sfc_chem_step_noalloc",
+                     "sfc_chem_submit",
                      "sfc_chem_poll", "sfc_chem_fetch", "sfc_chem_release", "sfc_chem_drain",
                      "sfc_chem_destroy"):
             getattr(L, name).restype = C.c_int
@@ -250,6 +253,13 @@ class Context:
         sp = C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
         self._check(lib().sfc_chem_step(self._h, C.byref(c), float(dt), int(precision), sp),
                     "sfc_chem_step")
+
+    def step_noalloc(self, cells: dict, dt: float, precision: int = FP64, stream=None) -> None:
+        """sfc_chem_step through the entry point that allocates nothing (at
+        most NOALLOC_MAX_CELLS cells; calls on one GPU must not overlap)."""
+        c = make_cells(cells)
+        self._check(lib().sfc_chem_step_noalloc(self._h, C.byref(c), float(dt), int(precision),
+                                                self._stream(stream)), "sfc_chem_step_noalloc")
 
     def step_nr(self, cells: dict, dt: float, stream=None) -> None:
         """Advance the cells with the Newton-Raphson comparator (binary64)."""

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -113,7 +114,31 @@ bool fill_par(const sfc_params& p, double z_default, double cd, const sfk::Net& 
   return true;
 }
 
+// Dispatch buffers of the entry point that allocates nothing
+// (sfc_chem_step_noalloc): a file-scope device array, one per GPU, holding
+// for a call of n <= kNoAllocMaxCells cells the work counter, the order
+// buckets, the cell order and the suspended-cell slots (layout_scratch).
+constexpr int64_t kNoAllocMaxCells = int64_t(1) << 21;
+
 constexpr size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// bytes of the dispatch buffers of an n-cell call, carved in this order:
+// work counter | order buckets | cell order | slot counter | rem | tiso |
+// cell | nsub | nit | fl | bucket
+constexpr size_t dispatch_bytes(int64_t n) {
+  return 256 + al256(size_t(sfk::kOrderWork) * 4) + al256(size_t(n) * 4) + 256 +
+         2 * al256(size_t(n) * 8) + 5 * al256(size_t(n) * 4);
+}
+constexpr size_t kScratchBytes = dispatch_bytes(kNoAllocMaxCells);  // 80.01 MiB
+
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// Device address of `scratch` per HIP device, taken once at the first
+// context created on that device (its host-side name is not an address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
 
 }  // namespace
 
@@ -136,6 +161,8 @@ struct sfc_ctx {
   int refill_min = 1;
   std::string last_error;
   sfserve::Server* server = nullptr;
+  void* scratch = nullptr;  // this device's copy of `scratch` (null if unavailable)
+  std::string scratch_error;
 };
 
 namespace {
@@ -320,6 +347,21 @@ int sfc_chem_init(const sfc_network* net_in, double z_default, double dust_cap_f
     release(ctx);
     return SFC_E_DEVICE;
   }
+  if (hip_device < kMaxDevices) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[hip_device] && g_scratch_err[hip_device] == hipSuccess) {
+      void* ptr = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e == hipSuccess && ptr) g_scratch_ptr[hip_device] = ptr;
+      else g_scratch_err[hip_device] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+    }
+    ctx->scratch = g_scratch_ptr[hip_device];
+    if (!ctx->scratch)
+      ctx->scratch_error = std::string("hipGetSymbolAddress: ") +
+                           hipGetErrorString(g_scratch_err[hip_device]);
+  } else {
+    ctx->scratch_error = "device index beyond the scratch table";
+  }
   if (const char* e = std::getenv("SFC_REFILL_MIN")) {
     const int v = std::atoi(e);
     if (v >= 1 && v <= 64) ctx->refill_min = v;
@@ -415,6 +457,22 @@ bool context_buffers(sfc_ctx* ctx, int64_t n, bool order, bool suspended, StepBu
     b.sus_cap = ctx->sus_cap;
   }
   return true;
+}
+
+// The same buffers for an n-cell call carved from this device's scratch
+// array (no allocation); the layout of dispatch_bytes.
+StepBuffers scratch_buffers(void* scratch_ptr, int64_t n) {
+  StepBuffers b;
+  char* p = static_cast<char*>(scratch_ptr);
+  b.counter = reinterpret_cast<unsigned long long*>(p);
+  p += 256;
+  b.buckets = reinterpret_cast<uint32_t*>(p);
+  p += al256(size_t(sfk::kOrderWork) * 4);
+  b.order = reinterpret_cast<int32_t*>(p);
+  p += al256(size_t(n) * 4);
+  b.sus = carve_suspended(p, n);
+  b.sus_cap = n;
+  return b;
 }
 
 // Plain path launch; method 0 = LI binary64, 1 = LI mixed, 2 = NR binary64.
@@ -514,6 +572,19 @@ int sfc_chem_step_nr(sfc_ctx* ctx, const sfc_cells* cells, double dt, void* hip_
   return step_launch(ctx, cells, dt, 2, hip_stream, "sfc_chem_step_nr");
 }
 
+int sfc_chem_step_noalloc(sfc_ctx* ctx, const sfc_cells* cells, double dt, int precision,
+                          void* hip_stream) {
+  if (!ctx) return SFC_E_INVAL;
+  if (precision != SFC_FP64 && precision != SFC_MIXED)
+    return fail(ctx, SFC_E_INVAL, "sfc_chem_step_noalloc: unknown precision");
+  if (!cells || cells->n < 0 || cells->n > kNoAllocMaxCells)
+    return fail(ctx, SFC_E_INVAL,
+                "sfc_chem_step_noalloc: at most " + std::to_string(kNoAllocMaxCells) +
+                    " cells per call (the scratch array's size)");
+  if (!ctx->scratch) return fail(ctx, SFC_E_DEVICE, "sfc_chem_step_noalloc: " + ctx->scratch_error);
+  const StepBuffers buf = scratch_buffers(ctx->scratch, cells->n);
+  return step_launch(ctx, cells, dt, precision, hip_stream, "sfc_chem_step_noalloc", &buf);
+}
 
 int sfc_chem_submit(sfc_ctx* ctx, const sfc_request* req, uint64_t* ticket) {
   if (!ctx || !req || !ticket) return SFC_E_INVAL;
