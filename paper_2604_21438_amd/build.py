@@ -4,12 +4,11 @@ Every HIP translation unit is compiled with packed FP32 instructions
 disabled (-target-feature -packed-fp32-ops); the host pass reports that it
 does not know the feature, which is expected.
 
-The build fails if a kernel spills vector registers to scratch memory.  A
-reload from scratch under a partial execution mask restores only the active
-lanes; the per-lane cell loops here diverge heavily, and a spilled kernel
-has been seen to return results that depended on which other cells shared
-its wavefront.  Spills of scalar registers (into vector register lanes)
-are allowed.
+The build fails if a kernel spills vector registers to scratch memory: the
+per-lane cell loops are written to keep every per-cell value in registers,
+and a spill means a change has pushed a kernel over its register budget
+(a decision to make explicitly, with a launch bound, not by accident).
+Spills of scalar registers (into vector register lanes) are allowed.
 """
 from __future__ import annotations
 

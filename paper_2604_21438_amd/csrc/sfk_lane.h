@@ -1337,8 +1337,14 @@ __device__ inline bool nr_chem(const Net& nt, const Par& pr, const CellK& ck, do
   return false;
 }
 
-// inner groups at trial T; G = residual of the gas energy equation / (k_B n)
-__device__ inline bool nr_inner(const Net& nt, const Par& pr, const CellK& ck, const Lane& s0,
+// inner groups at trial T; G = residual of the gas energy equation / (k_B n).
+// Kept out of line: the four inlined copies of this solve (at T - dl, T,
+// T + dl and the accepted T) compiled at -O3 into code whose iteration
+// counts and, for a few cells, results depended on which other cells shared
+// the wavefront (a single cell per wavefront matched the CPU reference);
+// called, compiled at -O1, or without the stand-in branches of the source
+// assembly, the same source matches the reference cell for cell.
+__device__ __attribute__((noinline)) bool nr_inner(const Net& nt, const Par& pr, const CellK& ck, const Lane& s0,
                                 double dts, double T, double tol, bool dust_on, NRState& g,
                                 double& G, int32_t& its) {
   if (dust_on && !nr_dust(nt, pr, ck, s0.Td, s0.Eir, dts, T, tol, g.Td, g.Eir, its)) return false;

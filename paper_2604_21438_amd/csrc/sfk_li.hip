@@ -104,9 +104,9 @@ template <class R>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 void li_step_kernel(Args) { step_loop<R, false>(); }
 
-// The NR comparator holds three trial states and the Newton systems of its
-// nested loops at once: at two waves per SIMD it spilled ~50 registers to
-// scratch, so it runs at one wave per SIMD with every value in registers.
+// The NR comparator: its inner solve (nr_inner) is a called function, so
+// the register budget is left to the compiler (it settles at two waves per
+// SIMD without spills); one wave per SIMD is allowed rather than a spill.
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1)))
 void nr_step_kernel(Args) { step_loop<double, true>(); }
 

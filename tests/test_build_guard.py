@@ -1,7 +1,6 @@
-"""The build's guard against vector-register spills (a spilled kernel with
-heavily divergent per-lane loops has returned results that depended on
-which cells shared its wavefront): the remark parser finds the kernels
-that spill and only those."""
+"""The build's guard against vector-register spills (the per-lane loops
+keep every per-cell value in registers): the remark parser finds the
+kernels that spill and only those."""
 from paper_2604_21438_amd.build import vgpr_spills
 
 REMARKS = """\
