@@ -41,12 +41,13 @@ BYTES_PER_CELL = 132          # 8 float64 reads, 7 float64 writes, 3 int32 write
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled
 # by what the same counter reads for a 256 MiB device-to-device copy
 # (bench.py --calibrate-copy 256).  Valid only for the plain-step sources
-# whose combined SHA-1 is given (sfk.h, sfk_lane.h, sfk_li.hip, in that
-# order): with any other source the figure is reported as null.
+# whose combined SHA-1 is given (sfk.h, sfk_lane.h, sfk_li.hip,
+# sfk_exp_table.h, in that order): with any other source the figure is
+# reported as null.
 TRAFFIC = {"kernel_sha1": "3c38136b4f318e7ec0848969acf02fed4ab6bc77",
            "fetch_bytes": 2.9282e9, "write_bytes": 9.0980e8}
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2604_21438_amd", "csrc", f)
-               for f in ("sfk.h", "sfk_lane.h", "sfk_li.hip")]
+               for f in ("sfk.h", "sfk_lane.h", "sfk_li.hip", "sfk_exp_table.h")]
 
 
 def kernel_sha1():

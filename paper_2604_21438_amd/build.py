@@ -81,7 +81,26 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), file=sys.stderr)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    build_probe(verbose)
     return LIB
+
+
+PROBE_SRC = os.path.join(ROOT, "tests", "math_probe.hip")
+PROBE_LIB = os.path.join(ROOT, "tests", "libmathprobe.so")
+
+
+def build_probe(verbose: bool = False) -> str:
+    """The tests' probe of the kernels' binary64 math (tests/math_probe.hip)."""
+    tmp = PROBE_LIB + ".tmp"
+    cmd = ["hipcc", *FLAGS, "-shared", "-o", tmp, PROBE_SRC]
+    if verbose:
+        print(" ".join(cmd), file=sys.stderr)
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0:
+        print(r.stdout, file=sys.stderr)
+        raise subprocess.CalledProcessError(r.returncode, cmd)
+    os.replace(tmp, PROBE_LIB)
+    return PROBE_LIB
 
 
 if __name__ == "__main__":

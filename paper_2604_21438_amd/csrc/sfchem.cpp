@@ -21,6 +21,7 @@ namespace {
 constexpr double KB = 1.380649e-16;
 constexpr double EV = 1.602176634e-12;
 constexpr double CL = 2.99792458e10;
+constexpr double ARAD = 7.5657e-15;
 
 // k_H2 / k_H3 at temperature T (host, binary64): used only to bound the
 // steady-state H- ratio over the temperature range of the rate fits.
@@ -67,6 +68,8 @@ bool fill_net(const sfc_network& in, sfk::Net& o) {
     return false;
   if (in.shield_mode == 1 && (!(in.shield_len > 0.0) || !(in.shield_b5 > 0.0))) return false;
   o.sh_b5 = in.shield_b5;
+  o.pe_ch = o.pm[3] * 1.3e-24 / KB;
+  o.pe_cr = o.pm[3] * 4.65e-30 / KB;
   o.pe_mode = in.pe_mode;
   o.shield_mode = in.shield_mode;
   return true;
@@ -102,6 +105,21 @@ bool fill_par(const sfc_params& p, double z_default, double cd, const sfk::Net& 
   //   = y_H2 sh_k sqrt(n_H T), rho = (1 + 4 y_He) m_H n_H
   constexpr double kGrav = 6.6743e-8, kMH = 1.67262192e-24, kPi = 3.14159265358979323846;
   o.sh_k = shield_len * std::sqrt(kPi * KB / (kGrav * kMH * kMH * (1.0 + 4.0 * p.y_he))) / 5.0e14;
+  // per-call constants of the kernels, formed once here
+  const double tc = p.t_cmb, tc2 = tc * tc, tc4 = tc * tc * tc * tc;
+  o.inv_f_chem = 1.0 / p.f_chem;
+  o.cr_a = p.c_red / ARAD;
+  o.eir_min = ARAD * tc2 * tc2 / p.c_red;
+  o.compton = net.pm[11] * 1.017e-37 * tc4 / KB;
+  {
+    // kappa(T) = kappa_max x^2 / (1 + x^2), x = T / T_norm, at T_CMB
+    const double x = tc * net.kap_tn, d = 1.0 + x * x;
+    const double k = net.kap_max * x * x / d;
+    const double dk = net.kap_max * 2.0 * x / (d * d) * net.kap_tn;
+    o.kir_fix = k;
+    o.absir_fix = k * (CL * ARAD) * (tc * tc) * (tc * tc);
+    o.betair_fix = k + dk * tc * 0.25;
+  }
   // bound of k_H2/k_H3 over [1, 1e8] K (fine log grid, 5 % margin)
   double mx = 0.0;
   for (int i = 0; i <= 8000; ++i) {

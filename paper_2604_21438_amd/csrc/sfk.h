@@ -29,6 +29,7 @@ struct Net {
   double x_c, x_o, f_oiii;
   double l_tul[5], l_a[5], l_g[5], l_qn[5], l_qe[5];
   double sh_b5;         // Doppler parameter of the H2 self-shielding fit [km/s]
+  double pe_ch, pe_cr;  // photoelectric heating and grain recombination prefactors / k_B
   int32_t pe_mode;      // 0 constant photoelectric efficiency, 1 grain charging
   int32_t shield_mode;  // 0 no H2 self-shielding, 1 local H2 column
 };
@@ -40,6 +41,12 @@ struct Par {
   double z_default;
   double hm_ratio_max;   // upper bound of y_H-/y_e = k_H2/k_H3 over the rate range
   double sh_k;           // H2 column / 5e14 cm^-2 = y_H2 sh_k sqrt(n_H T) (self-shielding)
+  // per-call constants, formed on the host
+  double inv_f_chem;     // 1 / f_chem
+  double cr_a;           // c~ / a_r: T_IR^4 = cr_a E_IR
+  double eir_min;        // a_r T_CMB^4 / c~: E_IR of FIXED IR and its floor
+  double compton;        // Lambda_12 / (k_B n_e (T - T_CMB)) [1/s]
+  double kir_fix, absir_fix, betair_fix;  // FIXED IR: kappa(T_CMB), kappa c a T_CMB^4, beta_IR
   int32_t n_cyc, n_sub_max, newton_max, ir_mode, thermal_mode, dust_mode;
   int32_t photon_absorb; // 1: attenuated photon densities written after the step
 };

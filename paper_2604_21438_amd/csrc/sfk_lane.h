@@ -79,26 +79,19 @@ __device__ inline double fsqrt(double x) {
   return fma(d, h, g);
 }
 
-// e^x in binary64.  x = (n/32) ln2 + r with n = rint(32 x / ln2), the
-// product n ln2/32 taken in two parts (the high part has 21 trailing zero
-// bits, so it is exact for |n| < 2^21, i.e. for every x whose result is
-// neither 0 nor infinite); then e^x = 2^(n >> 5) 2^((n & 31)/32) e^r with
-// |r| <= ln2/64, e^r - 1 from its Taylor series to r^6/720 (truncation
-// below 4e-18 relative), and 2^(j/32) (correctly rounded) from a 32-entry
-// table staged in LDS by each kernel (stage_tables).  Within one ulp of
-// e^x; 0 below the binary64 range, infinity above it.  About 16 VALU
-// instructions and one LDS read against ~21 for the library routine, whose
-// wider reduction interval needs a degree-11 polynomial.
-__constant__ double kExp2j32[32] = {
-    0x1.0000000000000p+0, 0x1.059b0d3158574p+0, 0x1.0b5586cf9890fp+0, 0x1.11301d0125b51p+0,
-    0x1.172b83c7d517bp+0, 0x1.1d4873168b9aap+0, 0x1.2387a6e756238p+0, 0x1.29e9df51fdee1p+0,
-    0x1.306fe0a31b715p+0, 0x1.371a7373aa9cbp+0, 0x1.3dea64c123422p+0, 0x1.44e086061892dp+0,
-    0x1.4bfdad5362a27p+0, 0x1.5342b569d4f82p+0, 0x1.5ab07dd485429p+0, 0x1.6247eb03a5585p+0,
-    0x1.6a09e667f3bcdp+0, 0x1.71f75e8ec5f74p+0, 0x1.7a11473eb0187p+0, 0x1.82589994cce13p+0,
-    0x1.8ace5422aa0dbp+0, 0x1.93737b0cdc5e5p+0, 0x1.9c49182a3f090p+0, 0x1.a5503b23e255dp+0,
-    0x1.ae89f995ad3adp+0, 0x1.b7f76f2fb5e47p+0, 0x1.c199bdd85529cp+0, 0x1.cb720dcef9069p+0,
-    0x1.d5818dcfba487p+0, 0x1.dfc97337b9b5fp+0, 0x1.ea4afa2a490dap+0, 0x1.f50765b6e4540p+0};
-__shared__ double lds_exp2j32[32];
+// e^x in binary64.  x = (n/512) ln2 + r with n = rint(512 x / ln2), the
+// product n ln2/512 taken in two parts (the high part has 21 trailing zero
+// bits, so it is exact for |n| < 2^21; every x whose result is neither 0
+// nor infinite has |n| < 5.6e5); then e^x = 2^(n >> 9) 2^((n & 511)/512) e^r
+// with |r| <= ln2/1024, e^r - 1 = r + r^2 (1/2 + r/6 + r^2/24) (truncation
+// below 2e-18 relative), and 2^(j/512) (each the nearest binary64, from
+// sfk_exp_table.h) read from a table staged in LDS by each kernel
+// (stage_tables).  Within one ulp of e^x; 0 below the binary64 range,
+// infinity above it.  About 14 VALU instructions and one LDS read against
+// ~21 for the library routine, whose wider reduction interval needs a
+// degree-11 polynomial.
+#include "sfk_exp_table.h"
+__shared__ double lds_exp2j512[512];
 
 // ln x in binary64 for positive normal x.  x = m 2^e with m in [0.5, 1);
 // c_j = 1/2 + j/256 is the node nearest m (j = 0..128), and with
@@ -244,22 +237,21 @@ __shared__ __attribute__((aligned(32))) double lds_logtab[129][4];
 // Every kernel that evaluates the per-lane code calls this first, with all
 // threads of the block (it ends with a barrier).
 __device__ inline void stage_tables() {
-  if (threadIdx.x < 32) lds_exp2j32[threadIdx.x] = kExp2j32[threadIdx.x];
+  for (unsigned i = threadIdx.x; i < 512u; i += blockDim.x) lds_exp2j512[i] = kExp2j512[i];
   for (unsigned i = threadIdx.x; i < 129u * 4u; i += blockDim.x)
     (&lds_logtab[0][0])[i] = (&kLogTab[0][0])[i];
   __syncthreads();
 }
 
 __device__ inline double fexp(double x) {
-  const double n = __builtin_rint(x * 46.16624130844683);  // 32 / ln2
-  double r = fma(-n, 0x1.62e42fee00000p-6, x);
-  r = fma(-n, 0x1.a39ef35793c76p-38, r);
-  const double q =
-      r * fma(r, fma(r, fma(r, fma(r, fma(r, 1.0 / 720.0, 1.0 / 120.0), 1.0 / 24.0), 1.0 / 6.0), 0.5),
-              1.0);
+  const double n = __builtin_rint(x * 738.6598609351493);  // 512 / ln2
+  double r = fma(-n, 0x1.62e42fee00000p-10, x);
+  r = fma(-n, 0x1.a39ef35793c76p-42, r);
+  const double p = fma(fma(r, 1.0 / 24.0, 1.0 / 6.0), r, 0.5);
+  const double q = fma(r * r, p, r);
   const int ni = int(n);
-  const double t = lds_exp2j32[ni & 31];
-  return __builtin_ldexp(fma(t, q, t), ni >> 5);
+  const double t = lds_exp2j512[ni & 511];
+  return __builtin_ldexp(fma(t, q, t), ni >> 9);
 }
 
 __device__ inline double flog(double x) {
@@ -642,7 +634,7 @@ __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, d
   // H8 formation on grains (T_d frozen) and Gamma_1 (0.2 + 4.2 f eV)
   {
     const R Td = R(Td_);
-    const R fa = M::dv(R(1), R(1) + M::ea(750.0 * (1.0 / 75.0 - 1.0 / Td_)));
+    const R fa = M::dv(R(1), R(1) + M::ea(750.0 * (1.0 / 75.0 - frcp(Td_))));
     const R s = M::sq(T + Td);
     const R D = R(1) + R(0.04) * s + R(2e-3) * T + R(8e-6) * T * T;
     const R iD = M::dv(R(1), D);
@@ -700,11 +692,11 @@ __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, d
       const R deps = R(-0.0487 * 4e-3 * 0.73) * p73 * ipsi * ia * ia -
                      R(0.0365 * 2e-4) * tt * ib * ib;  // d eps / d psi
       const R deps_t = R(0.0365 * 0.7) * tt * iT * ib;
-      const R ch = R(nt.pm[3] * 1.3e-24 / KB * ck.g4 * ck.fd);
+      const R ch = R(nt.pe_ch * ck.g4 * ck.fd);
       const R beta = R(0.735) * M::ea(-0.068 * lnT64);
       const R pb = M::ea(double(beta) * lnpsi);
       const R t94 = M::ea(0.94 * lnT64);
-      const R cr = R(nt.pm[3] * 4.65e-30 / KB * ck.n * ck.fd);
+      const R cr = R(nt.pe_cr * ck.n * ck.fd);
       const R rec = cr * ye * t94 * pb;
       const R rec_e = cr * t94 * pb * (floored ? R(1) : R(1) - beta);
       const R rec_t = rec * (R(0.94) * iT - R(0.068) * beta * iT * R(lnpsi) + beta * R(0.5) * iT);
@@ -754,8 +746,7 @@ __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, d
   }
   // Lambda_12, Compton cooling off the CMB
   {
-    const double tc4 = pr.t_cmb * pr.t_cmb * pr.t_cmb * pr.t_cmb;
-    const R cc = R(nt.pm[11] * 1.017e-37 * tc4 / KB);
+    const R cc = R(pr.compton);
     acc(q, R(-1), TF<R>{R(double(cc) * (T64 - pr.t_cmb)), cc}, YE);
   }
   // Lambda_13, line cooling: two-level coolants (stand-in)
@@ -844,19 +835,17 @@ __device__ inline void dust_eval(const Net& nt, const Par& pr, double Tg_, doubl
   const R ctil = R(pr.c_red * CL);
   if (pr.ir_mode == 1) {
     const R E = R(Eir_);
-    const R tir = M::sq(M::sq(R(pr.c_red / ARAD) * E));
+    const R tir = M::sq(M::sq(R(pr.cr_a) * E));
     R ki, dki;
     kappa<R>(nt, tir, ki, dki);
     d.kir = ki;
     d.absir = ki * ctil * E;
     d.betair = ki + dki * tir * R(0.25);
   } else {
-    const R tc = R(pr.t_cmb);
-    R ki, dki;
-    kappa<R>(nt, tc, ki, dki);
-    d.kir = ki;
-    d.absir = ki * R(CL * ARAD) * (tc * tc) * (tc * tc);
-    d.betair = ki + dki * tc * R(0.25);
+    // FIXED: T_IR = T_CMB, constants of the call
+    d.kir = R(pr.kir_fix);
+    d.absir = R(pr.absir_fix);
+    d.betair = R(pr.betair_fix);
   }
   const R td2 = Td * Td;
   d.emis = kd * R(ARAD * CL) * td2 * td2;
@@ -1155,8 +1144,7 @@ __device__ inline void dust_floors(const Par& pr, Lane& L) {
   const double cv = KB * L.ck.n * cvk(pr, L.y2, L.ye);
   if (L.E < cv * pr.t_cmb) { L.E = cv * pr.t_cmb; L.fl |= F_FLOOR; }
   if (pr.ir_mode == 1) {
-    const double tc2 = pr.t_cmb * pr.t_cmb;
-    const double emin = ARAD * tc2 * tc2 / pr.c_red;
+    const double emin = pr.eir_min;
     if (L.Eir < emin) { L.Eir = emin; L.fl |= F_FLOOR; }
   }
 }
@@ -1187,7 +1175,7 @@ __device__ bool subcycle(const Net& nt, const Par& pr, Lane& L) {
     nu_dust = fmax(nu_dust, fabs(double(d.Sg)) * frcp(alpha * T));
     if (pr.ir_mode == 1) nu_dust = fmax(nu_dust, fabs(double(d.Sir)) * frcp(L.Eir));
   }
-  const bool tight = dust_on && (L.rem * nu_dust / pr.f_chem >= double(pr.n_cyc));
+  const bool tight = dust_on && (L.rem * nu_dust * pr.inv_f_chem >= double(pr.n_cyc));
   if (tight) L.fl |= F_TIGHT;
 
   const double iEk = frcp(Ek);
@@ -1501,8 +1489,7 @@ __device__ inline int64_t resume_cell(const Net& nt, const Par& pr, const Cells&
   L.ye = c.y_e[i];
   L.E = c.eint[i];
   L.Td = c.tdust[i];
-  const double tc2 = pr.t_cmb * pr.t_cmb;
-  L.Eir = pr.ir_mode == 1 ? c.eir[i] : ARAD * tc2 * tc2 / pr.c_red;
+  L.Eir = pr.ir_mode == 1 ? c.eir[i] : pr.eir_min;
   cell_consts(nt, pr, c.nh[i], c.n_euv[i], c.n_fuv[i], c.zmet ? c.zmet[i] : pr.z_default, L.ck);
   L.rem = s.rem[p];
   L.Tiso = s.tiso[p];
@@ -1522,8 +1509,7 @@ __device__ bool load_cell(const Net& nt, const Par& pr, const Cells& c, int64_t 
   L.ye = c.y_e[i];
   L.E = c.eint[i];
   L.Td = c.tdust[i];
-  const double tc2 = pr.t_cmb * pr.t_cmb;
-  L.Eir = pr.ir_mode == 1 ? c.eir[i] : ARAD * tc2 * tc2 / pr.c_red;
+  L.Eir = pr.ir_mode == 1 ? c.eir[i] : pr.eir_min;
   bool ok = finite_bits(nh) && nh > 0.0 && finite_bits(ne) && ne >= 0.0 && finite_bits(nf) &&
             nf >= 0.0 && finite_bits(z) && z >= 0.0 && finite_bits(L.y2) && L.y2 >= 0.0 &&
             finite_bits(L.ye) && L.ye >= 0.0 && finite_bits(L.E) && L.E > 0.0 &&
