@@ -31,11 +31,13 @@ sys.path.insert(0, ROOT)
 
 # algorithmic operations per subcycle of the LI update (add/sub, mul, div,
 # sqrt with a multiply-add counted as 2, plus 44 transcendental calls counted
-# as 1 each), from the counting build of the CPU reference on a seeded
-# sample of this workload: python -m oracle.count_ops
-FLOP_PER_SUBCYCLE = 1539.0
+# as 1 each, and the tight dust solve's Newton iterations), from the counting
+# build of the CPU reference on a seeded sample of this workload with E_IR
+# evolved: python -m oracle.count_ops; with the IR field held (FIXED), 1539
+FLOP_PER_SUBCYCLE = 1695.0
+FLOP_PER_SUBCYCLE_FIXED_IR = 1539.0
 PEAK_FP64_VALU = 78.6e12      # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
-BYTES_PER_CELL = 132          # 8 float64 reads, 7 float64 writes, 3 int32 writes
+BYTES_PER_CELL = 148          # 9 float64 reads, 8 float64 writes, 3 int32 writes (E_IR evolved)
 # HBM bytes of one binary64 step on the 128^3 workload (the two launches of
 # the LI kernel under progress dispatch, first pass and resumed pass), from
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled
@@ -63,7 +65,7 @@ def measured_traffic():
     if TRAFFIC["kernel_sha1"] is None or TRAFFIC["kernel_sha1"] != kernel_sha1():
         return None
     return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
-STATE_KEYS = ("y_h2", "y_e", "eint", "tdust")
+STATE_KEYS = ("y_h2", "y_e", "eint", "tdust", "eir")
 
 
 def log(*a):
@@ -358,7 +360,7 @@ def collapse_leg(sfc):
     tracks = {}
     for name, factor, method in (("li_factor1", 1.0, "li"), ("li_factor1000", 1000.0, "li"),
                                  ("nr_factor1", 1.0, "nr")):
-        ctx = sfc.Context(dust_factor=factor)
+        ctx = sfc.Context(dust_factor=factor, params=sfc.default_params(ir_mode=sfc.IR_FIXED))
         t0 = time.perf_counter()
         tr = CO.run(CO.gpu_step(ctx, method), CO.initial_parcels())
         el = time.perf_counter() - t0
@@ -404,11 +406,14 @@ def gmc_leg(args, sfc, W, torch):
     order = bc_order()
     out = dict(cells_per_level=sizes, cell_updates_per_coarse_step=updates)
     factors = (1.0, 1000.0) if args.gmc_both_factors else (1.0,)
+    if args.gmc_factor is not None:
+        factors = (args.gmc_factor,)
+    precs = ((sfc.FP64, "fp64"),) if args.gmc_no_mixed else ((sfc.FP64, "fp64"), (sfc.MIXED, "mixed"))
     for factor in factors:
         ctx = sfc.Context(dust_factor=factor, z_default=0.1,
                           served_budget_bytes=args.served_budget_mib << 20)
         legs = {}
-        for prec, pname in ((sfc.FP64, "fp64"), (sfc.MIXED, "mixed")):
+        for prec, pname in precs:
             if prec == sfc.FP64 and not args.gmc_skip_plain:
                 restore()
                 t0 = time.perf_counter()
@@ -417,67 +422,87 @@ def gmc_leg(args, sfc, W, torch):
                 torch.cuda.synchronize()
                 el = time.perf_counter() - t0
                 legs[f"plain_{pname}"] = dict(value=updates / el, seconds=el)
-            restore()
-            remaining = [2 ** L for L in range(nl)]
-            inflight = [None] * nl
-            lat = []
-            t0 = time.perf_counter()
-            while any(remaining) or any(t is not None for t in inflight):
-                for L in range(nl):
-                    if inflight[L] is not None:
-                        r = ctx.poll(inflight[L])
-                        if r is not None:
-                            lat.append(r["t_done"] - r["t_submit"])
-                            inflight[L] = None
-                    if inflight[L] is None and remaining[L] > 0:
-                        inflight[L] = ctx.submit(bufs[L], levels[L]["dt"], prec, level=L,
-                                                 sync=False)
-                        remaining[L] -= 1
-                time.sleep(100e-6)
-            el = time.perf_counter() - t0
-            legs[f"served_{pname}"] = dict(value=updates / el, seconds=el,
-                                           latency_ms=dict(p50=pct(lat, 50) * 1e3,
-                                                           p99=pct(lat, 99) * 1e3,
-                                                           max=float(np.max(lat)) * 1e3))
-            log(f"[bench] gmc factor {factor:g} {pname}: served {el:.2f} s")
-            # the same with each level's state resident under a block key:
-            # the first substep uploads, the others continue in the arena
-            # (no copy-in, no copy-out); the results are fetched at the end
-            restore()
-            remaining = [2 ** L for L in range(nl)]
-            inflight = [None] * nl
-            last = [None] * nl
-            lat = []
-            t0 = time.perf_counter()
-            while any(remaining) or any(t is not None for t in inflight):
-                for L in range(nl):
-                    if inflight[L] is not None:
-                        r = ctx.poll(inflight[L])
-                        if r is not None:
-                            lat.append(r["t_done"] - r["t_submit"])
-                            inflight[L] = None
-                    if inflight[L] is None and remaining[L] > 0:
-                        first = remaining[L] == 2 ** L
-                        inflight[L] = ctx.submit(bufs[L] if first else None, levels[L]["dt"],
-                                                 prec, level=L, sync=False,
-                                                 block_key=1 + L, resume=not first)
-                        last[L] = inflight[L]
-                        remaining[L] -= 1
-                time.sleep(100e-6)
-            for L in range(nl):
-                ctx.fetch(last[L], bufs[L])
-            torch.cuda.synchronize()
-            el = time.perf_counter() - t0
-            for L in range(nl):
-                ctx.release(1 + L)
-            legs[f"served_{pname}_resident"] = dict(
-                value=updates / el, seconds=el,
-                latency_ms=dict(p50=pct(lat, 50) * 1e3, p99=pct(lat, 99) * 1e3,
-                                max=float(np.max(lat)) * 1e3))
-            log(f"[bench] gmc factor {factor:g} {pname}: served, resident blocks {el:.2f} s")
+                log(f"[bench] gmc factor {factor:g} {pname}: plain {el:.2f} s")
+            if args.gmc_served in ("both", "copy"):
+                legs.update(gmc_served_copy(ctx, bufs, levels, prec, pname, factor, restore,
+                                            updates))
+            if args.gmc_served in ("both", "resident"):
+                legs.update(gmc_served_resident(ctx, bufs, levels, prec, pname, factor, restore,
+                                                updates, torch))
         ctx.close()
         out[f"dust_factor_{factor:g}"] = legs
     return out
+
+
+def gmc_served_copy(ctx, bufs, levels, prec, pname, factor, restore, updates):
+    """Served GMC step, every request copied in and out of the arena."""
+    nl = len(levels)
+    legs = {}
+    restore()
+    remaining = [2 ** L for L in range(nl)]
+    inflight = [None] * nl
+    lat = []
+    t0 = time.perf_counter()
+    while any(remaining) or any(t is not None for t in inflight):
+        for L in range(nl):
+            if inflight[L] is not None:
+                r = ctx.poll(inflight[L])
+                if r is not None:
+                    lat.append(r["t_done"] - r["t_submit"])
+                    inflight[L] = None
+            if inflight[L] is None and remaining[L] > 0:
+                inflight[L] = ctx.submit(bufs[L], levels[L]["dt"], prec, level=L,
+                                         sync=False)
+                remaining[L] -= 1
+        time.sleep(100e-6)
+    el = time.perf_counter() - t0
+    legs[f"served_{pname}"] = dict(value=updates / el, seconds=el,
+                                   latency_ms=dict(p50=pct(lat, 50) * 1e3,
+                                                   p99=pct(lat, 99) * 1e3,
+                                                   max=float(np.max(lat)) * 1e3))
+    log(f"[bench] gmc factor {factor:g} {pname}: served {el:.2f} s")
+    return legs
+
+
+def gmc_served_resident(ctx, bufs, levels, prec, pname, factor, restore, updates, torch):
+    """The same with each level's state resident under a block key: the
+    first substep uploads, the others continue in the arena (no copy-in, no
+    copy-out); the results are fetched at the end."""
+    nl = len(levels)
+    legs = {}
+    restore()
+    remaining = [2 ** L for L in range(nl)]
+    inflight = [None] * nl
+    last = [None] * nl
+    lat = []
+    t0 = time.perf_counter()
+    while any(remaining) or any(t is not None for t in inflight):
+        for L in range(nl):
+            if inflight[L] is not None:
+                r = ctx.poll(inflight[L])
+                if r is not None:
+                    lat.append(r["t_done"] - r["t_submit"])
+                    inflight[L] = None
+            if inflight[L] is None and remaining[L] > 0:
+                first = remaining[L] == 2 ** L
+                inflight[L] = ctx.submit(bufs[L] if first else None, levels[L]["dt"],
+                                         prec, level=L, sync=False,
+                                         block_key=1 + L, resume=not first)
+                last[L] = inflight[L]
+                remaining[L] -= 1
+        time.sleep(100e-6)
+    for L in range(nl):
+        ctx.fetch(last[L], bufs[L])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    for L in range(nl):
+        ctx.release(1 + L)
+    legs[f"served_{pname}_resident"] = dict(
+        value=updates / el, seconds=el,
+        latency_ms=dict(p50=pct(lat, 50) * 1e3, p99=pct(lat, 99) * 1e3,
+                        max=float(np.max(lat)) * 1e3))
+    log(f"[bench] gmc factor {factor:g} {pname}: served, resident blocks {el:.2f} s")
+    return legs
 
 
 def grid256_leg(args, sfc, W, torch):
@@ -556,6 +581,13 @@ def main():
                     help="GMC leg: served runs only (no plain per-level baseline)")
     ap.add_argument("--gmc-both-factors", action="store_true",
                     help="run the GMC leg at dust factor 1000 too")
+    ap.add_argument("--gmc-factor", type=float, default=None,
+                    help="run the GMC leg at this dust factor only")
+    ap.add_argument("--gmc-served", choices=("both", "copy", "resident", "none"), default="both",
+                    help="GMC leg: which served runs (copy in/out per request, resident "
+                         "block keys, both, or none)")
+    ap.add_argument("--gmc-no-mixed", action="store_true",
+                    help="GMC leg: binary64 only")
     ap.add_argument("--hii-cells", type=int, default=262144,
                     help="cells of the H II region stand-in leg (0 skips it)")
     ap.add_argument("--nr-cells", type=int, default=262144,
@@ -667,7 +699,8 @@ def main():
         "config": {
             "workload": "grid128: 128^3 = 2,097,152 independent cells, log n_H ~ U[0,8], "
                         "log T ~ U[1,4], T_d = T, Z in {0.01,0.1,1}, dt = 10 kyr, "
-                        "dust factor 1 (C_d = 1e4 erg/g/K), IR fixed",
+                        "dust factor 1 (C_d = 1e4 erg/g/K), E_IR evolved (T_IR log-uniform "
+                        "in [T_CMB, T_d])",
             "cells": n, "dt_s": dt, "dust_factor": 1.0, "precision": "fp64",
             "dispatch": "progress", "phase_nsub": int(sfc.default_params().phase_nsub),
         },
@@ -689,6 +722,18 @@ def main():
         },
         "stats_fp64": d64,
     }
+
+    # ---- the same step with the IR field held at the CMB's (FIXED IR) ----
+    if not args.no_sweep:
+        c = sfc.Context(dust_factor=1.0, params=sfc.default_params(ir_mode=sfc.IR_FIXED))
+        s, ks, o = run(c, sfc.FP64, 1, 0, "fp64 factor 1 fixed IR")
+        c.close()
+        dd = describe(o)
+        result["fixed_ir"] = dict(value=n / s, kernel_s=ks, nsub=dd["nsub"],
+                                  tight_fraction=dd["tight_fraction"],
+                                  flop_per_subcycle=FLOP_PER_SUBCYCLE_FIXED_IR,
+                                  roofline_frac=FLOP_PER_SUBCYCLE_FIXED_IR * dd["subcycles"] / ks /
+                                  PEAK_FP64_VALU)
 
     # ---- dust-capacity sweep ----
     if not args.no_sweep:

@@ -132,7 +132,7 @@ typedef struct {
   int32_t n_cyc;       /* subcycle limit deciding tight coupling [300]    */
   int32_t n_sub_max;   /* hard cap on subcycles per call [100000]         */
   int32_t newton_max;  /* tight dust Newton iteration cap [60]            */
-  int32_t ir_mode;     /* sfc_ir_mode [SFC_IR_FIXED]                      */
+  int32_t ir_mode;     /* sfc_ir_mode [SFC_IR_EVOLVE]                     */
   int32_t thermal_mode;/* sfc_thermal_mode [SFC_THERMAL_EVOLVE]           */
   int32_t dust_mode;   /* sfc_dust_mode [SFC_DUST_EVOLVE]                 */
   int32_t dispatch;    /* sfc_dispatch [SFC_DISPATCH_PROGRESS]            */

@@ -14,9 +14,10 @@ transcendentals nudged up / uncontracted and nudged down),
 ``liborc_rcp.so`` / ``liborc_rcpdn.so`` (every quotient formed as a
 product with a reciprocal moved one ulp up, contracted / down,
 uncontracted), ``liborc_all.so`` (all of these classes at once) and
-``liborc_c32.so`` (exponentials and powers rounded to binary32).  The six
-alternative builds only measure each cell's
-conditioning: to binary64 rounding, and to coefficients of binary32
+``liborc_c32.so`` (exponentials and powers rounded to binary32) and
+``liborc_j32.so`` (the Jacobian of the chemistry + energy solve rounded to
+binary32).  The alternative builds only measure each cell's conditioning:
+to binary64 rounding, and to coefficients and partials of binary32
 accuracy.
 """
 from __future__ import annotations
@@ -47,6 +48,10 @@ LIB_ALL = os.path.join(HERE, "liborc_all.so")
 # exponentials and powers rounded to binary32, everything else binary64:
 # the error floor of binary32 rate coefficients (mixed-precision bar)
 LIB_C32 = os.path.join(HERE, "liborc_c32.so")
+# the partial derivatives of the chemistry + energy system (its Jacobian)
+# rounded to binary32 before the solve, everything else binary64: the
+# rounding of the mixed path's binary32 partials (mixed-precision bar)
+LIB_J32 = os.path.join(HERE, "liborc_j32.so")
 SRC = os.path.join(HERE, "orc_chem.cpp")
 
 NREAC, NPROC, NLINE = 12, 14, 5
@@ -67,7 +72,7 @@ def build(force: bool = True) -> None:
                 (LIB_RCP, ["-DORC_RCP", "-mfma", "-ffp-contract=fast"]),
                 (LIB_RCPDN, ["-DORC_RCP", "-DORC_NUDGE_DOWN"]),
                 (LIB_ALL, ["-DORC_RCP", "-DORC_NUDGE", "-mfma", "-ffp-contract=fast"]),
-                (LIB_C32, ["-DORC_COEF32"]))
+                (LIB_C32, ["-DORC_COEF32"]), (LIB_J32, ["-DORC_JAC32"]))
     for out, extra in variants:
         if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(SRC):
             continue
@@ -128,7 +133,7 @@ _libs: dict = {}
 
 def _lib(counting: bool = False, variant: str = "plain"):
     """The plain build, or a named rounding variant ("fma", "dn", "rcp",
-    "rcpdn", "all", "c32"), or any other
+    "rcpdn", "all", "c32", "j32"), or any other
     build of the same source given by its path (the pins' mutation test
     builds copies with planted mistakes)."""
     if variant.endswith(".so"):
@@ -136,7 +141,7 @@ def _lib(counting: bool = False, variant: str = "plain"):
     else:
         path = LIB_COUNT if counting else {"fma": LIB_FMA, "dn": LIB_DN, "rcp": LIB_RCP,
                                        "rcpdn": LIB_RCPDN, "all": LIB_ALL,
-                                       "c32": LIB_C32}.get(variant, LIB)
+                                       "c32": LIB_C32, "j32": LIB_J32}.get(variant, LIB)
     if path not in _libs:
         if variant.endswith(".so"):
             if not os.path.exists(path):
@@ -239,7 +244,7 @@ def li_step(cells: dict, dt: float, net: Network | None = None, params: Params |
             nthreads: int = 1, variant: str = "plain") -> dict:
     """LI update of every cell over dt [s]; returns a new dict of arrays.
     variant names another rounding of the same arithmetic ("fma", "dn",
-    "rcp", "rcpdn", "all", "c32"; see build)."""
+    "rcp", "rcpdn", "all", "c32", "j32"; see build)."""
     net = net or default_network()
     params = params or default_params()
     out, n = _prepare(cells, params.ir_mode, params.photon_absorb)
@@ -346,24 +351,28 @@ def _rel(a, b, floor=1e-20):
 def rounding_spread(cells: dict, dt: float, ref: dict, net=None, params=None,
                     nthreads: int = 1, method: str = "li") -> np.ndarray:
     """Per cell, the largest relative change of any output between the
-    reference result `ref` and seven other valid roundings of the same
+    reference result `ref` and seven (nine with E_IR evolved) other valid roundings of the same
     computation: the contracted build with transcendentals nudged up; the
     uncontracted build with them nudged down and powers formed as
     exp(y log x); quotients formed through a reciprocal moved one ulp up
     (contracted) or down (uncontracted); all of the first kinds at once
     (contracted, transcendentals and reciprocals one ulp up); and the input
-    internal energy moved by one unit in the last place either way.  A cell whose spread exceeds a
-    tolerance is not determined to that tolerance by binary64 arithmetic.
-    Cells that the reference marks invalid (NaN outputs) have spread 0 here;
-    comparisons treat them separately."""
+    internal energy moved by one unit in the last place either way, and so
+    the IR energy density when it evolves (the two energies of the state
+    that enter temperatures through a root or a ratio).  A cell whose spread
+    exceeds a tolerance is not determined to that tolerance by binary64
+    arithmetic.  Cells that the reference marks invalid (NaN outputs) have
+    spread 0 here; comparisons treat them separately."""
     params = params or default_params()
     step = li_step if method == "li" else nr_step
     alt = [step(cells, dt, net, params, nthreads, variant=v)
            for v in ("fma", "dn", "rcp", "rcpdn", "all")]
-    for direction in (np.inf, -np.inf):
-        nudged = dict(cells)
-        nudged["eint"] = np.nextafter(np.asarray(cells["eint"], np.float64), direction)
-        alt.append(step(nudged, dt, net, params, nthreads))
+    energies = ["eint"] + (["eir"] if params.ir_mode == IR_EVOLVE and "eir" in cells else [])
+    for key in energies:
+        for direction in (np.inf, -np.inf):
+            nudged = dict(cells)
+            nudged[key] = np.nextafter(np.asarray(cells[key], np.float64), direction)
+            alt.append(step(nudged, dt, net, params, nthreads))
     spread = np.zeros(ref["nsub"].shape[0])
     invalid = (np.asarray(ref["flags"]) & F_INVALID) != 0
     for o in alt:
@@ -396,6 +405,22 @@ def coefficient_sensitivity(cells: dict, dt: float, ref: dict, net=None, params=
     move the result.  Invalid cells get 0."""
     params = params or default_params()
     o = li_step(cells, dt, net, params, nthreads, variant="c32")
+    s = np.zeros(ref["nsub"].shape[0])
+    invalid = (np.asarray(ref["flags"]) & F_INVALID) != 0
+    for k in OUT_KEYS:
+        s = np.maximum(s, np.where(invalid, 0.0, _rel(o[k], ref[k])))
+    return s
+
+
+def jacobian_sensitivity(cells: dict, dt: float, ref: dict, net=None, params=None,
+                         nthreads: int = 1) -> np.ndarray:
+    """Per cell, the largest relative output change when the Jacobian of
+    every chemistry + energy solve is rounded to binary32 (the sources and
+    the solve stay binary64): how far partials of binary32 accuracy alone
+    move the result, which a near-singular I - h J amplifies.  Invalid
+    cells get 0."""
+    params = params or default_params()
+    o = li_step(cells, dt, net, params, nthreads, variant="j32")
     s = np.zeros(ref["nsub"].shape[0])
     invalid = (np.asarray(ref["flags"]) & F_INVALID) != 0
     for k in OUT_KEYS:

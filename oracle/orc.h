@@ -86,7 +86,7 @@ typedef struct {
   int32_t n_cyc;       /* subcycle limit deciding "tight"        [300]   */
   int32_t n_sub_max;   /* hard cap on subcycles per call         [100000]*/
   int32_t newton_max;  /* tight-case Newton iteration cap        [60]    */
-  int32_t ir_mode;     /* ORC_IR_FIXED / ORC_IR_EVOLVE           [FIXED] */
+  int32_t ir_mode;     /* ORC_IR_FIXED / ORC_IR_EVOLVE          [EVOLVE] */
   int32_t thermal_mode;/* ORC_THERMAL_*                          [EVOLVE]*/
   int32_t dust_mode;   /* ORC_DUST_*                             [EVOLVE]*/
   int32_t photon_absorb; /* 1: attenuate N_EUV, N_FUV over dt after the

@@ -498,7 +498,18 @@ struct Dust {
   real kd, betad;         /* kappa(T_d), beta_d                          */
   real absir, betair;     /* kappa(T_IR) c~ E_IR, beta_IR                */
   real Sd, Sir, Sg, alpha;/* sources; alpha_g = c_v / rho                */
+  real sd_noise, sir_noise; /* rounding level of S_d and S_IR (dust_rate) */
 };
+
+/* Reading (the dust timescale at radiative equilibrium): near equilibrium
+ * the net sources S_d and S_IR are differences of terms many orders of
+ * magnitude larger than themselves, each known to a few units in the last
+ * place, so their computed values are rounding noise; Eq.
+ * timescale_of_dust would then take its step limit from that noise.  A net
+ * source within SRC_NOISE of the sum of its gross terms (64 ulps) sets no
+ * timescale: the rate entering Eq. timescale_of_dust is |S| minus that
+ * level, floored at zero (continuous in S). */
+const double SRC_NOISE = 64.0 * 2.220446049250313e-16;
 
 static void dust_eval(const orc_network& net, const orc_params& p, real Tg, real Td, real Eir,
                       real cv, const Cell& c, Dust& d) {
@@ -528,10 +539,13 @@ static void dust_eval(const orc_network& net, const orc_params& p, real Tg, real
   }
   real td4 = Td * Td * Td * Td;
   real emis = kd * A_RAD * C_LIGHT * td4;
-  d.Sd = d.absir + c.e_uv - emis - d.G * d.gd * (Td - Tg);
+  real coup = d.G * d.gd * (Td - Tg);
+  d.Sd = d.absir + c.e_uv - emis - coup;
   d.Sir = c.rho * c.fd * (emis - d.absir);
   d.Sg = d.G * c.fd * d.gd * (Td - Tg);
   d.alpha = cv / c.rho;
+  d.sd_noise = SRC_NOISE * (rabs(d.absir) + rabs(real(c.e_uv)) + rabs(emis) + rabs(coup));
+  d.sir_noise = SRC_NOISE * (c.rho * c.fd) * (rabs(emis) + rabs(d.absir));
 }
 
 /* Gaussian elimination with partial pivoting (ties: lowest row). */
@@ -844,9 +858,9 @@ static uint32_t dust_floors(const orc_params& p, const Cell& c, State& s) {
 
 /* inverse dust timescale, Eq. timescale_of_dust (gas side: gas-grain only) */
 static real dust_rate(const orc_params& p, const Dust& d, real Td, real Tg, real Eir) {
-  real nu = rabs(d.Sd) / (p.dust_cap * Td);
+  real nu = rmax(rabs(d.Sd) - d.sd_noise, real(0.0)) / (p.dust_cap * Td);
   nu = rmax(nu, rabs(d.Sg) / (d.alpha * Tg));
-  if (p.ir_mode == ORC_IR_EVOLVE) nu = rmax(nu, rabs(d.Sir) / Eir);
+  if (p.ir_mode == ORC_IR_EVOLVE) nu = rmax(nu, rmax(rabs(d.Sir) - d.sir_noise, real(0.0)) / Eir);
   return nu;
 }
 
@@ -1042,6 +1056,11 @@ static void li_cell(const orc_network& net, const orc_params& p, const orc_cells
         J[2][1] = (co.q.e + co.q.t * dTdye) / Eref;
         J[2][2] = co.q.t * dTdu3 / Eref;
       }
+#ifdef ORC_JAC32
+      /* measurement build: partials of binary32 accuracy (mixed bar) */
+      for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) J[r][k] = real(double(float(rval(J[r][k]))));
+#endif
       real A[3][3], b[3], x[3] = {0.0, 0.0, 0.0};
       for (int r = 0; r < 3; ++r) {
         for (int k = 0; k < 3; ++k) A[r][k] = (r == k ? real(1.0) : real(0.0)) - h * J[r][k];
@@ -1441,7 +1460,7 @@ void orc_params_default(orc_params* p) {
   p->n_cyc = 300;
   p->n_sub_max = 100000;
   p->newton_max = 60;
-  p->ir_mode = ORC_IR_FIXED;
+  p->ir_mode = ORC_IR_EVOLVE;
   p->thermal_mode = ORC_THERMAL_EVOLVE;
   p->dust_mode = ORC_DUST_EVOLVE;
 }

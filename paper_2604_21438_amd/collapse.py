@@ -11,6 +11,11 @@ gravity (its Bonnor-Ebert tests), which are out of scope here: the tracks
 T_g(n), T_d(n), y_H2(n) show how the pseudo dust heat capacity and the
 LI scheme behave along a collapse, qualitatively.
 
+The parcels carry no IR field: the one-zone model has no transport to
+carry the grains' emission away, so it is run with FIXED IR (the IR field
+held at the CMB's, an optically thin parcel); an E_IR evolved inside the
+parcel alone would keep all the energy the grains radiate.
+
 The compression is plain binary64 numpy arithmetic on the host, identical
 whichever implementation advances the chemistry: `step(cells, dt)` is any
 callable that returns the advanced cell dict (the library's plain path, its

@@ -298,7 +298,7 @@ void sfc_params_default(sfc_params* p) {
   p->n_cyc = 300;
   p->n_sub_max = 100000;
   p->newton_max = 60;
-  p->ir_mode = SFC_IR_FIXED;
+  p->ir_mode = SFC_IR_EVOLVE;
   p->thermal_mode = SFC_THERMAL_EVOLVE;
   p->dust_mode = SFC_DUST_EVOLVE;
   p->dispatch = SFC_DISPATCH_PROGRESS;
@@ -347,9 +347,9 @@ int sfc_chem_init(const sfc_network* net_in, double z_default, double dust_cap_f
     return SFC_E_DEVICE;
   }
   ctx->cus = prop.multiProcessorCount;
-  ctx->bpc[0] = sfk::max_blocks_per_cu(0);
-  ctx->bpc[1] = sfk::max_blocks_per_cu(1);
-  ctx->bpc[2] = sfk::max_blocks_per_cu(2);
+  ctx->bpc[0] = sfk::max_blocks_per_cu(0, sfk::stand_ins(knet));
+  ctx->bpc[1] = sfk::max_blocks_per_cu(1, sfk::stand_ins(knet));
+  ctx->bpc[2] = sfk::max_blocks_per_cu(2, sfk::stand_ins(knet));
   if (hipMalloc(&ctx->d_counter, sizeof(unsigned long long)) != hipSuccess) {
     delete ctx;
     return SFC_E_NOMEM;

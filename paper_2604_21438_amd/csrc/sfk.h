@@ -95,10 +95,17 @@ struct Args {
 };
 
 // host-callable launchers (defined in sfk_li.hip)
+// True when the network switches on a piece beside the solver (H2
+// self-shielding or the grain-charge photoelectric heating).  Those pieces
+// are compiled into separate kernel instantiations, so that the default
+// kernels carry none of their code and none of their register pressure;
+// the launches pick the instantiation from the network.
+inline bool stand_ins(const Net& n) { return n.shield_mode == 1 || n.pe_mode == 1; }
+
 hipError_t launch_step(const Args& a, int precision, int grid, hipStream_t s);
 hipError_t launch_step_nr(const Args& a, int grid, hipStream_t s);  // binary64 NR comparator
 hipError_t launch_reset(unsigned long long* counter, hipStream_t s);
-int max_blocks_per_cu(int precision);  // 0 LI binary64, 1 LI mixed, 2 NR
+int max_blocks_per_cu(int precision, bool stand_ins);  // 0 LI binary64, 1 LI mixed, 2 NR
 // Density dispatch: order[0..n) = the densest quarter of the cells (all of
 // them with all_dense) by decreasing half-octave of n_H, then the rest in
 // index order (n < 2^31; work holds kOrderWork uint32 counters).

@@ -51,6 +51,7 @@ constexpr double RG = 5.83e-8;    // gas-grain coefficient (Appendix C)
 constexpr double THIGH = 1000.0;
 constexpr double TLOW = 75.0;
 constexpr double EVK = 1.602176634e-12 / 1.380649e-16;  // eV / k_B [K]
+constexpr double kSrcNoise = 64.0 * 2.220446049250313e-16;  // 64 ulps (dust timescale)
 
 // ------------------------------------------------------------------ math
 // 1/x for positive, finite, normal x: hardware estimate and two Newton
@@ -487,8 +488,11 @@ __device__ inline void acc(Acc<R>& A, R s, TF<R> k, D<R, M> x) {
 // rate and the heating / cooling it drives) are added to the three
 // accumulators at once.  Temperature, 1/T, ln T, the fit polynomials and
 // every exponent argument are binary64 in both precisions; R is the type
-// of the exponentials' results and of the products and partials.
-template <class R>
+// of the exponentials' results and of the products and partials.  kS
+// compiles in the pieces beside the solver that the network can switch on
+// (H2 self-shielding, grain-charge photoelectric heating); without it their
+// branches, and the registers they hold, are gone.
+template <class R, bool kS>
 __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, double Td_,
                          double Tin, const CellK& ck, Chem<R>& out) {
   using M = Mth<R>;
@@ -650,7 +654,7 @@ __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, d
     const R k9 = R(ck.k9), k10 = R(ck.k10), k11 = R(ck.k11);
     acc(re, k9 + k11, TF<R>{R(1), R(0)}, YH);
     acc(q, R(nt.pm[1] * nt.g2k) * k9, TF<R>{R(1), R(0)}, YH);
-    if (nt.shield_mode == 1) {
+    if (kS && nt.shield_mode == 1) {
       // H2 self-shielding (stand-in, the fit of Draine & Bertoldi 1996):
       // f = 0.965 / (1 + x/b5)^2 + 0.035 / s exp(-8.5e-4 s), s = sqrt(1 + x),
       // x = y_H2 sh_k sqrt(n_H T) (local column of shield_len Jeans lengths)
@@ -671,7 +675,7 @@ __device__ void assemble(const Net& nt, const Par& pr, double y2d, double yed, d
       acc(rh2, -k10, TF<R>{R(1), R(0)}, Y2);
       acc(q, R(nt.pm[2] * nt.g3k) * k10, TF<R>{R(1), R(0)}, Y2);
     }
-    if (nt.pe_mode != 1) {
+    if (!kS || nt.pe_mode != 1) {
       q.v = q.v + ck.g4;
     } else if (ck.g4 > 0.0) {
       // photoelectric heating with grain charging and the cooling by
@@ -1150,7 +1154,7 @@ __device__ inline void dust_floors(const Par& pr, Lane& L) {
 }
 
 // One subcycle; returns true when the cell has covered its interval.
-template <class R>
+template <class R, bool kS>
 __device__ bool subcycle(const Net& nt, const Par& pr, Lane& L) {
   const bool iso = pr.thermal_mode == 1;
   const bool dust_on = (pr.dust_mode == 0) && !iso;
@@ -1161,7 +1165,7 @@ __device__ bool subcycle(const Net& nt, const Par& pr, Lane& L) {
   const double T = iso ? L.Tiso : Ek * pr.gm1 * intr;
 
   Chem<R> ch;
-  assemble<R>(nt, pr, L.y2, L.ye, L.Td, T, L.ck, ch);
+  assemble<R, kS>(nt, pr, L.y2, L.ye, L.Td, T, L.ck, ch);
   const double f0 = double(ch.f[0]), f1 = double(ch.f[1]), fq = double(ch.f[2]);
 
   double nu_dust = 0.0, qgg = 0.0;
@@ -1171,9 +1175,19 @@ __device__ bool subcycle(const Net& nt, const Par& pr, Lane& L) {
     // gas-grain exchange rho S_g / (k_B n) [K/s]
     qgg = double(d.Sg) * (L.ck.rho / knb);
     const double alpha = knb * (ntr * pr.igm1) * frcp(L.ck.rho);
-    nu_dust = fabs(double(d.Sd)) * frcp(pr.cd * L.Td);
+    // Near radiative equilibrium S_d and S_IR are differences of terms far
+    // larger than themselves, known to a few ulps each: a net source within
+    // kSrcNoise of its gross terms is rounding noise and sets no timescale
+    // (|S| minus that level, floored at 0)
+    const double absir = fabs(double(d.absir)), emis = fabs(double(d.emis));
+    const double sd_noise =
+        kSrcNoise * (absir + fabs(L.ck.euv) + emis + fabs(double(d.G) * double(d.gd) * (L.Td - T)));
+    nu_dust = fmax(fabs(double(d.Sd)) - sd_noise, 0.0) * frcp(pr.cd * L.Td);
     nu_dust = fmax(nu_dust, fabs(double(d.Sg)) * frcp(alpha * T));
-    if (pr.ir_mode == 1) nu_dust = fmax(nu_dust, fabs(double(d.Sir)) * frcp(L.Eir));
+    if (pr.ir_mode == 1) {
+      const double sir_noise = kSrcNoise * (L.ck.rho * L.ck.fd) * (emis + absir);
+      nu_dust = fmax(nu_dust, fmax(fabs(double(d.Sir)) - sir_noise, 0.0) * frcp(L.Eir));
+    }
   }
   const bool tight = dust_on && (L.rem * nu_dust * pr.inv_f_chem >= double(pr.n_cyc));
   if (tight) L.fl |= F_TIGHT;
@@ -1297,13 +1311,14 @@ __device__ inline bool nr_dust(const Net& nt, const Par& pr, const CellK& ck, do
 
 // group (iii): (y_H2, y_e) at fixed T_g, T_d; steps that would leave the
 // bounds are damped towards them
+template <bool kS>
 __device__ inline bool nr_chem(const Net& nt, const Par& pr, const CellK& ck, double y20,
                                double ye0, double dts, double T, double Td, double tol,
                                double& y2, double& ye, int32_t& its) {
   for (int it = 1; it <= 20; ++it) {
     ++its;
     Chem<double> ch;
-    assemble<double>(nt, pr, y2, ye, Td, T, ck, ch);
+    assemble<double, kS>(nt, pr, y2, ye, Td, T, ck, ch);
     const double F1 = y2 - y20 - dts * ch.f[0];
     const double F2 = ye - ye0 - dts * ch.f[1];
     const double J11 = 1.0 - dts * ch.J[0][0], J12 = -(dts * ch.J[0][1]);
@@ -1332,13 +1347,14 @@ __device__ inline bool nr_chem(const Net& nt, const Par& pr, const CellK& ck, do
 // the wavefront (a single cell per wavefront matched the CPU reference);
 // called, compiled at -O1, or without the stand-in branches of the source
 // assembly, the same source matches the reference cell for cell.
+template <bool kS>
 __device__ __attribute__((noinline)) bool nr_inner(const Net& nt, const Par& pr, const CellK& ck, const Lane& s0,
                                 double dts, double T, double tol, bool dust_on, NRState& g,
                                 double& G, int32_t& its) {
   if (dust_on && !nr_dust(nt, pr, ck, s0.Td, s0.Eir, dts, T, tol, g.Td, g.Eir, its)) return false;
-  if (!nr_chem(nt, pr, ck, s0.y2, s0.ye, dts, T, g.Td, tol, g.y2, g.ye, its)) return false;
+  if (!nr_chem<kS>(nt, pr, ck, s0.y2, s0.ye, dts, T, g.Td, tol, g.y2, g.ye, its)) return false;
   Chem<double> ch;
-  assemble<double>(nt, pr, g.y2, g.ye, g.Td, T, ck, ch);
+  assemble<double, kS>(nt, pr, g.y2, g.ye, g.Td, T, ck, ch);
   const double knb = KB * ck.n;
   double gas_grain = 0.0;
   if (dust_on) {
@@ -1352,6 +1368,7 @@ __device__ __attribute__((noinline)) bool nr_inner(const Net& nt, const Par& pr,
 
 // One backward-Euler substep of length dts from L; on success L holds the
 // new state.  Outer iterations are counted in L.nit, inner ones in its.
+template <bool kS>
 __device__ bool nr_substep_iter(const Net& nt, const Par& pr, Lane& L, double dts,
                                 int32_t& its) {
   const bool iso = pr.thermal_mode == 1;
@@ -1361,7 +1378,7 @@ __device__ bool nr_substep_iter(const Net& nt, const Par& pr, Lane& L, double dt
   NRState g{L.y2, L.ye, iso ? L.Tiso : L.E / (knb * cvk(pr, L.y2, L.ye)), L.Td, L.Eir};
   if (iso) {
     double Gv;
-    if (!nr_inner(nt, pr, L.ck, s0, dts, L.Tiso, 1e-5, dust_on, g, Gv, its)) return false;
+    if (!nr_inner<kS>(nt, pr, L.ck, s0, dts, L.Tiso, 1e-5, dust_on, g, Gv, its)) return false;
     L.y2 = g.y2;
     L.ye = g.ye;
     L.Td = g.Td;
@@ -1378,9 +1395,9 @@ __device__ bool nr_substep_iter(const Net& nt, const Par& pr, Lane& L, double dt
     const double dl = 1e-4 * T;
     NRState gm = g, gc = g, gp = g;
     double Gm, Gc, Gp;
-    if (!nr_inner(nt, pr, L.ck, s0, dts, T - dl, tol, dust_on, gm, Gm, its)) return false;
-    if (!nr_inner(nt, pr, L.ck, s0, dts, T, tol, dust_on, gc, Gc, its)) return false;
-    if (!nr_inner(nt, pr, L.ck, s0, dts, T + dl, tol, dust_on, gp, Gp, its)) return false;
+    if (!nr_inner<kS>(nt, pr, L.ck, s0, dts, T - dl, tol, dust_on, gm, Gm, its)) return false;
+    if (!nr_inner<kS>(nt, pr, L.ck, s0, dts, T, tol, dust_on, gc, Gc, its)) return false;
+    if (!nr_inner<kS>(nt, pr, L.ck, s0, dts, T + dl, tol, dust_on, gp, Gp, its)) return false;
     const double dG = (Gp - Gm) / (2.0 * dl);
     double Tn = T - Gc / dG;
     bool limited = false;
@@ -1395,7 +1412,7 @@ __device__ bool nr_substep_iter(const Net& nt, const Par& pr, Lane& L, double dt
     g.T = Tn;
     if (ok) {
       double Gv;
-      if (!nr_inner(nt, pr, L.ck, s0, dts, Tn, tol, dust_on, g, Gv, its)) return false;
+      if (!nr_inner<kS>(nt, pr, L.ck, s0, dts, Tn, tol, dust_on, g, Gv, its)) return false;
       L.y2 = g.y2;
       L.ye = g.ye;
       L.Td = g.Td;
@@ -1410,9 +1427,10 @@ __device__ bool nr_substep_iter(const Net& nt, const Par& pr, Lane& L, double dt
 // One substep; L.nit counts every Newton iteration of it: outer iterations
 // and the inner dust/IR and chemistry iterations (so two runs take the same
 // iteration path only if every convergence test came out the same).
+template <bool kS>
 __device__ bool nr_substep(const Net& nt, const Par& pr, Lane& L, double dts) {
   int32_t its = 0;
-  const bool ok = nr_substep_iter(nt, pr, L, dts, its);
+  const bool ok = nr_substep_iter<kS>(nt, pr, L, dts, its);
   L.nit += its;
   return ok;
 }
@@ -1424,11 +1442,12 @@ constexpr uint32_t F_NRFAIL = 32u;
 // failure, max(lev - 1, 0) on success.  L.rem holds dt, tsub and lev the
 // driver state.  At most n_sub_max attempts (then NRFAIL), so every cell
 // ends.  Returns true when the cell is done.
+template <bool kS>
 __device__ bool nr_attempt(const Net& nt, const Par& pr, Lane& L, double& tsub, int& lev,
                            int& attempts) {
   const double dts = (L.rem - tsub) / ldexp(1.0, lev);
   Lane trial = L;
-  const bool ok = nr_substep(nt, pr, trial, dts);
+  const bool ok = nr_substep<kS>(nt, pr, trial, dts);
   L.nit = trial.nit;
   ++attempts;
   if (ok) {

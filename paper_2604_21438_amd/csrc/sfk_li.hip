@@ -21,7 +21,7 @@ constexpr unsigned kStash = 64;
 
 // kNR selects the Newton-Raphson comparator instead of the LI subcycle
 // (binary64 only); both share the lane refill, stash and dispatch.
-template <class R, bool kNR>
+template <class R, bool kNR, bool kS>
 __device__ __attribute__((always_inline)) inline void step_loop() {
   stage_tables();
   const int lane = threadIdx.x & 63;
@@ -80,8 +80,8 @@ __device__ __attribute__((always_inline)) inline void step_loop() {
     }
     if (busy == 0) break;
     if (cell >= 0) {
-      const bool done = kNR ? nr_attempt(fresh(a.netc), fresh(a.parc), L, tsub, lev, attempts)
-                            : subcycle<R>(fresh(a.netc), fresh(a.parc), L);
+      const bool done = kNR ? nr_attempt<kS>(fresh(a.netc), fresh(a.parc), L, tsub, lev, attempts)
+                            : subcycle<R, kS>(fresh(a.netc), fresh(a.parc), L);
       if (done) {
         store_cell<R>(fresh(a.netc), fresh(a.parc), a.c, cell, L, a.dt);
         cell = -1;
@@ -99,16 +99,19 @@ __device__ __attribute__((always_inline)) inline void step_loop() {
   }
 }
 
-// The LI kernels at two waves per SIMD (their register peak fits 256).
-template <class R>
+// The LI kernels at two waves per SIMD at least (binary64 peaks at ~220
+// registers; mixed fits three waves without the stand-in pieces).  kS: the
+// network's stand-in pieces compiled in (stand_ins()).
+template <class R, bool kS>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
-void li_step_kernel(Args) { step_loop<R, false>(); }
+void li_step_kernel(Args) { step_loop<R, false, kS>(); }
 
 // The NR comparator: its inner solve (nr_inner) is a called function, so
 // the register budget is left to the compiler (it settles at two waves per
 // SIMD without spills); one wave per SIMD is allowed rather than a spill.
+template <bool kS>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1)))
-void nr_step_kernel(Args) { step_loop<double, true>(); }
+void nr_step_kernel(Args) { step_loop<double, true, kS>(); }
 
 __global__ void reset_kernel(unsigned long long* counter) { *counter = 0ull; }
 
@@ -342,15 +345,23 @@ __global__ __launch_bounds__(256) void progress_scatter_kernel(Suspended sus, ui
 }  // namespace
 
 hipError_t launch_step(const Args& a, int precision, int grid, hipStream_t s) {
-  if (precision == 1)
-    hipLaunchKernelGGL((li_step_kernel<float>), dim3(grid), dim3(kBlock), 0, s, a);
+  const bool si = stand_ins(a.net);
+  if (precision == 1 && si)
+    hipLaunchKernelGGL((li_step_kernel<float, true>), dim3(grid), dim3(kBlock), 0, s, a);
+  else if (precision == 1)
+    hipLaunchKernelGGL((li_step_kernel<float, false>), dim3(grid), dim3(kBlock), 0, s, a);
+  else if (si)
+    hipLaunchKernelGGL((li_step_kernel<double, true>), dim3(grid), dim3(kBlock), 0, s, a);
   else
-    hipLaunchKernelGGL((li_step_kernel<double>), dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((li_step_kernel<double, false>), dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_step_nr(const Args& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((nr_step_kernel), dim3(grid), dim3(kBlock), 0, s, a);
+  if (stand_ins(a.net))
+    hipLaunchKernelGGL((nr_step_kernel<true>), dim3(grid), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL((nr_step_kernel<false>), dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
@@ -359,18 +370,20 @@ hipError_t launch_reset(unsigned long long* counter, hipStream_t s) {
   return hipGetLastError();
 }
 
-int max_blocks_per_cu(int precision) {
+namespace {
+template <class K>
+int blocks_per_cu(K kernel) {
   int nb = 0;
-  if (precision == 2)
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, nr_step_kernel, kBlock,
-                                                       0);
-  else if (precision == 1)
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, li_step_kernel<float>, kBlock,
-                                                       0);
-  else
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, li_step_kernel<double>, kBlock,
-                                                       0);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBlock, 0);
   return nb > 0 ? nb : 1;
+}
+}  // namespace
+
+int max_blocks_per_cu(int precision, bool si) {
+  if (precision == 2) return si ? blocks_per_cu(nr_step_kernel<true>) : blocks_per_cu(nr_step_kernel<false>);
+  if (precision == 1)
+    return si ? blocks_per_cu(li_step_kernel<float, true>) : blocks_per_cu(li_step_kernel<float, false>);
+  return si ? blocks_per_cu(li_step_kernel<double, true>) : blocks_per_cu(li_step_kernel<double, false>);
 }
 
 hipError_t launch_order(const double* nh, int64_t n, bool all_dense, int32_t* order,

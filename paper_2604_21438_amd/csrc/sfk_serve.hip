@@ -196,7 +196,7 @@ __device__ inline void set_level_prio(int lvl, int& prio) {
 // leave when their lanes are done (each cell is bounded by n_sub_max
 // subcycles), so every wave reaches an exit and the newer launch, whose
 // waves take the freed slots, serves all new work.
-template <class R>
+template <class R, bool kS>
 __global__ __launch_bounds__(kBlock) void served_drain_kernel(ServedArgs) {
   stage_tables();
   const int lane = threadIdx.x & 63;
@@ -269,7 +269,7 @@ __global__ __launch_bounds__(kBlock) void served_drain_kernel(ServedArgs) {
     }
     if (a.level_prio) set_level_prio(cell >= 0 ? int((tk >> kLevelShift) & 0xff) : -1, prio);
     if (cell >= 0) {
-      if (subcycle<R>(fresh(a.netc), fresh(a.parc), L)) {
+      if (subcycle<R, kS>(fresh(a.netc), fresh(a.parc), L)) {
         store_cell<R>(fresh(a.netc), fresh(a.parc), a.arena, cell, L);
         cell = -1;
         pend = tk + 1;
@@ -343,20 +343,33 @@ __global__ __launch_bounds__(64) void arm_kernel(ArmArgs a) {
 
 }  // namespace
 
-int served_blocks_per_cu(int precision) {
+namespace {
+template <class K>
+int drain_blocks_per_cu(K kernel) {
   int nb = 0;
-  if (precision == 1)
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, served_drain_kernel<float>, kBlock, 0);
-  else
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, served_drain_kernel<double>, kBlock, 0);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBlock, 0);
   return nb > 0 ? nb : 1;
+}
+}  // namespace
+
+int served_blocks_per_cu(int precision, bool si) {
+  if (precision == 1)
+    return si ? drain_blocks_per_cu(served_drain_kernel<float, true>)
+              : drain_blocks_per_cu(served_drain_kernel<float, false>);
+  return si ? drain_blocks_per_cu(served_drain_kernel<double, true>)
+            : drain_blocks_per_cu(served_drain_kernel<double, false>);
 }
 
 hipError_t launch_served(const ServedArgs& a, int precision, int grid, hipStream_t s) {
-  if (precision == 1)
-    hipLaunchKernelGGL(served_drain_kernel<float>, dim3(grid), dim3(kBlock), 0, s, a);
+  const bool si = stand_ins(a.net);
+  if (precision == 1 && si)
+    hipLaunchKernelGGL((served_drain_kernel<float, true>), dim3(grid), dim3(kBlock), 0, s, a);
+  else if (precision == 1)
+    hipLaunchKernelGGL((served_drain_kernel<float, false>), dim3(grid), dim3(kBlock), 0, s, a);
+  else if (si)
+    hipLaunchKernelGGL((served_drain_kernel<double, true>), dim3(grid), dim3(kBlock), 0, s, a);
   else
-    hipLaunchKernelGGL(served_drain_kernel<double>, dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((served_drain_kernel<double, false>), dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 

@@ -77,7 +77,7 @@ struct ArmArgs {
 };
 
 // host-callable launchers (defined in sfk_serve.hip)
-int served_blocks_per_cu(int precision);
+int served_blocks_per_cu(int precision, bool stand_ins);
 hipError_t launch_served(const ServedArgs& a, int precision, int grid, hipStream_t s);
 hipError_t launch_copy_in(const CopyArgs& a, hipStream_t s);
 hipError_t launch_copy_out(const CopyArgs& a, hipStream_t s);

@@ -468,7 +468,7 @@ Server* create(const Config& cfg, std::string* err, int* code) {
     a.level_prio = env_num("SFC_SERVE_LEVEL_PRIO", 1.0) != 0.0 ? 1 : 0;
     a.netc = cfg.netc;
     a.parc = cfg.parc;
-    q.grid = cus * sfk::served_blocks_per_cu(prec);
+    q.grid = cus * sfk::served_blocks_per_cu(prec, sfk::stand_ins(cfg.net));
     for (int i = 0; i < 2; ++i) {
       a.slot = i;
       if (hipStreamBeginCapture(s->drain_stream[0], hipStreamCaptureModeThreadLocal) != hipSuccess)

@@ -16,6 +16,12 @@ Every population is a dict of contiguous float64 numpy arrays (SoA):
   y_e    electron abundance per H nucleus
   eint   gas internal energy density [erg cm^-3]
   tdust  dust temperature [K]
+  eir    IR radiation energy density [erg cm^-3] (read when E_IR evolves)
+
+The IR field is drawn as a radiation temperature log-uniform between
+T_CMB = 2.73 K and the cell's dust temperature (a field diluted below the
+dust's own emission), E_IR = (c / c~) a T_IR^4 with c~/c = 1e-4, the
+default reduced speed of light.
 
 The internal energy is built from a drawn gas temperature with the ideal-gas
 relation E = k_B n_H (1 - y_H2 + y_e + y_He) T / (gamma - 1), y_He = 0.1,
@@ -29,12 +35,15 @@ from __future__ import annotations
 import numpy as np
 
 KB = 1.380649e-16
+A_RAD = 7.5657e-15        # radiation constant [erg cm^-3 K^-4]
+C_RED = 1.0e-4            # reduced speed of light / c (default)
+T_CMB = 2.73
 Y_HE = 0.1
 GAMMA = 5.0 / 3.0
 YR = 3.15576e7            # Julian year [s]
 KYR = 1.0e3 * YR
 
-FIELDS = ("nh", "n_euv", "n_fuv", "zmet", "y_h2", "y_e", "eint", "tdust")
+FIELDS = ("nh", "n_euv", "n_fuv", "zmet", "y_h2", "y_e", "eint", "tdust", "eir")
 
 
 def _streams(cfg_index: int, nstreams: int, seed_offset: int = 0):
@@ -62,7 +71,7 @@ def uniform_population(n: int, cfg_index: int = 0, z_choices=None, seed_offset: 
     """Independent cells: log10 n_H ~ U[0,8], log10 T ~ U[1,4], T_d = T,
     log10 y_H2 ~ U[-6,-0.3], log10 y_H+ ~ U[-8,-1], y_H- = 1e-12, y_e from
     charge neutrality, log10 N_EUV, log10 N_FUV ~ U[-5,1] independently,
-    Z = 1 or drawn uniformly from z_choices."""
+    Z = 1 or drawn uniformly from z_choices, E_IR as in the module notes."""
     g = _streams(cfg_index, 8, seed_offset)
     nh = 10.0 ** g[0].uniform(0.0, 8.0, n)
     tg = 10.0 ** g[1].uniform(1.0, 4.0, n)
@@ -73,12 +82,18 @@ def uniform_population(n: int, cfg_index: int = 0, z_choices=None, seed_offset: 
         zmet = np.ones(n)
     else:
         zmet = np.asarray(z_choices, np.float64)[g[6].integers(0, len(z_choices), n)]
-    return _pack(nh, n_euv, n_fuv, zmet, y_h2, y_e, tg, tg.copy())
+    return _pack(nh, n_euv, n_fuv, zmet, y_h2, y_e, tg, tg.copy(), g[7].uniform(0.0, 1.0, n))
 
 
-def _pack(nh, n_euv, n_fuv, zmet, y_h2, y_e, tg, td):
+def ir_energy(tdust, u):
+    """E_IR for a radiation temperature T_CMB (td / T_CMB)^u, u in [0, 1]."""
+    tir = T_CMB * (np.maximum(tdust, T_CMB) / T_CMB) ** u
+    return A_RAD * tir ** 4 / C_RED
+
+
+def _pack(nh, n_euv, n_fuv, zmet, y_h2, y_e, tg, td, u_ir):
     out = dict(nh=nh, n_euv=n_euv, n_fuv=n_fuv, zmet=zmet, y_h2=y_h2, y_e=y_e,
-               eint=internal_energy(nh, y_h2, y_e, tg), tdust=td)
+               eint=internal_energy(nh, y_h2, y_e, tg), tdust=td, eir=ir_energy(td, u_ir))
     return {k: np.ascontiguousarray(v, dtype=np.float64) for k, v in out.items()}
 
 
@@ -118,7 +133,7 @@ def hii_region(n: int = 262_144, dt_yr: float = 100.0):
       - n_H and T carry 5 % log-normal scatter; Z = 1.
     dt = 100 yr stands for the step of a reduced-speed-of-light (1e-4 c)
     radiation solver on a ~0.01 pc cell, which the paper does not state."""
-    g = _streams(5, 4)
+    g = _streams(5, 4)  # g[3]: E_IR
     x = g[0].uniform(-3.0, 3.0, (n, 3))
     r = np.maximum(np.sqrt(np.sum(x * x, axis=1)), 0.05)
     r_st, w = 2.67, 0.05
@@ -134,7 +149,8 @@ def hii_region(n: int = 262_144, dt_yr: float = 100.0):
     flux = 1.36e49 / (4.0 * np.pi * (r * PC) ** 2 * C_LIGHT)
     n_euv = flux * front
     n_fuv = 0.5 * flux
-    return _pack(nh, n_euv, n_fuv, np.ones(n), y_h2, y_e, tg, td), dt_yr * YR
+    return _pack(nh, n_euv, n_fuv, np.ones(n), y_h2, y_e, tg, td, g[3].uniform(0.0, 1.0, n)), \
+        dt_yr * YR
 
 
 def subsample(cells: dict, m: int, seed: int = 7):
@@ -213,9 +229,10 @@ def grid256(n: int | None = None, side: int = 256):
                     (i // (side * side) + 0.5) * h], axis=1)
     n_euv = point_source_field(pos, src, amp, h)
     n_fuv = point_source_field(pos, src, amp * ratio, h)
+    u_ir = g[8].uniform(0.0, 1.0, full)
     sl = slice(0, m)
-    return _pack(nh[sl], n_euv, n_fuv, np.ones(m), y_h2[sl], y_e[sl], tg[sl], tg[sl].copy()), \
-        10.0 * KYR
+    return _pack(nh[sl], n_euv, n_fuv, np.ones(m), y_h2[sl], y_e[sl], tg[sl], tg[sl].copy(),
+                 u_ir[sl]), 10.0 * KYR
 
 
 BLOCK = 8  # AMR block edge (8^3 = 512 cells)
@@ -365,6 +382,7 @@ def gmc_levels(target_cells: int = 4_000_000, base_side: int = 64, n_levels: int
         y_h2, y_e = _abundances(g[5], g[6], m)
         n_euv = point_source_field(pos, src, amp, h0)
         n_fuv = point_source_field(pos, src, amp * ratio, h0)
-        cells = _pack(nh, n_euv, n_fuv, np.full(m, zmet), y_h2, y_e, tg, tg.copy())
+        cells = _pack(nh, n_euv, n_fuv, np.full(m, zmet), y_h2, y_e, tg, tg.copy(),
+                      g[7].uniform(0.0, 1.0, m))
         out.append(dict(cells=cells, dt=10.0 * KYR / 2.0 ** L, blocks=dens.shape[0], level=L))
     return out

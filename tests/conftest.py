@@ -22,8 +22,10 @@ def cell_dict(nh, tgas, tdust, y_h2, y_e, n_euv=0.0, n_fuv=0.0, z=1.0, eir=None)
     nh, tgas, tdust, y_h2, y_e, n_euv, n_fuv, z = [np.ascontiguousarray(a.copy()) for a in arrs]
     d = dict(nh=nh, n_euv=n_euv, n_fuv=n_fuv, zmet=z, y_h2=y_h2, y_e=y_e,
              eint=internal_energy(nh, y_h2, y_e, tgas), tdust=tdust)
-    if eir is not None:
-        d["eir"] = np.ascontiguousarray(np.broadcast_to(np.asarray(eir, np.float64), nh.shape).copy())
+    if eir is None:  # the CMB's field (the value FIXED IR holds), evolved from there
+        from paper_2604_21438_amd.workloads import A_RAD, C_RED, T_CMB
+        eir = A_RAD * T_CMB ** 4 / C_RED
+    d["eir"] = np.ascontiguousarray(np.broadcast_to(np.asarray(eir, np.float64), nh.shape).copy())
     return d
 
 

@@ -90,7 +90,7 @@ def report(errs, exc, n, label="", gpu=None, ref=None, cells=None):
 
 
 FP64_TOL = 1e-9
-# A cell counts as determined by binary64 arithmetic when none of six other
+# A cell counts as determined by binary64 arithmetic when none of the other
 # valid roundings of the reference (oracle.rounding_spread) moves any of its
 # outputs by more than EXEMPT_SPREAD; such cells must match to FP64_TOL with
 # the same subcycle count and flags.  A cell that rounding alone moves
@@ -175,17 +175,18 @@ def assert_fp64_parity(gpu, cells, dt, onet, opar, label=""):
 
 
 MIXED_TOL = 1e-4
-# A cell is determined to binary32-coefficient accuracy when neither a 1e-6
-# relative change of every subcycle nor rounding the reference's
-# exponentials and powers to binary32 moves any output by more than
-# MIXED_WELL (oracle.step_sensitivity, oracle.coefficient_sensitivity).
+# A cell is determined to binary32 accuracy when neither a 1e-6 relative
+# change of every subcycle, nor rounding the reference's exponentials and
+# powers to binary32, nor rounding its chemistry + energy Jacobian to
+# binary32 moves any output by more than MIXED_WELL
+# (oracle.step_sensitivity, coefficient_sensitivity, jacobian_sensitivity).
 MIXED_WELL = 1e-6
 
 
 def check_mixed_bar(gpu, ref, cells, dt, onet, opar, label="", bar=True):
     """The mixed bar against the binary64 reference: p99 <= MIXED_TOL on
     every output, and max <= MIXED_TOL over the cells determined to
-    binary32-coefficient accuracy; the cells beyond MIXED_TOL are counted.
+    binary32 accuracy (coefficients and partials); the cells beyond MIXED_TOL are counted.
     With bar=False the same figures are only printed.  Conservation holds
     to round-off (the update is binary64) in either case."""
     errs, exc = compare(gpu, ref)
@@ -200,10 +201,11 @@ def check_mixed_bar(gpu, ref, cells, dt, onet, opar, label="", bar=True):
             assert np.percentile(e, 99) <= MIXED_TOL, (label, k, float(np.percentile(e, 99)))
     sens = oracle.step_sensitivity(cells, dt, ref, onet, opar, host_threads())
     c32 = oracle.coefficient_sensitivity(cells, dt, ref, onet, opar, host_threads())
+    j32 = oracle.jacobian_sensitivity(cells, dt, ref, onet, opar, host_threads())
     worst = np.where(valid, worst_of(errs, n), 0.0)
-    well = valid & (np.maximum(sens, c32) <= MIXED_WELL)
+    well = valid & (np.maximum(np.maximum(sens, c32), j32) <= MIXED_WELL)
     print(f"[mixed] {label}: beyond 1e-4: {int((worst > MIXED_TOL).sum())}/{n} cells; determined "
-          f"to binary32-coefficient accuracy: {int(well.sum())}, max err there "
+          f"to binary32 accuracy: {int(well.sum())}, max err there "
           f"{worst[well].max() if well.any() else 0:.2e}; the rest: max "
           f"{worst[valid & ~well].max() if (valid & ~well).any() else 0:.2e}", flush=True)
     if bar and well.any():

@@ -15,12 +15,13 @@ pytestmark = pytest.mark.gpu
 def test_collapse_track_matches_reference(method, factor):
     import paper_2604_21438_amd as sfc
     print(f"[gpu collapse] {method} factor {factor}", flush=True)
-    ctx = sfc.Context(dust_factor=factor)
+    par = sfc.default_params(ir_mode=sfc.IR_FIXED)  # optically thin parcel
+    ctx = sfc.Context(dust_factor=factor, params=par)
     try:
         gpu = CO.run(CO.gpu_step(ctx, method), CO.initial_parcels())
     finally:
         ctx.close()
-    onet, opar = oracle_net_params(sfc.default_network(), sfc.default_params(), factor)
+    onet, opar = oracle_net_params(sfc.default_network(), par, factor)
     f = oracle.nr_step if method == "nr" else oracle.li_step
     ref = CO.run(lambda c, dt: f(c, dt, onet, opar, 4), CO.initial_parcels())
     assert gpu["nh"].shape == ref["nh"].shape

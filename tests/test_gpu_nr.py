@@ -4,7 +4,7 @@ CPU reference's NR on the same seeded cells.
 NR stops each loop at a relative tolerance (1e-5, 1e-3 after 10 outer
 iterations), so where binary64 rounding flips a convergence decision the
 result moves by up to that tolerance.  Bar: cells the reference determines
-to 1e-10 (rounding spread over six other valid roundings of the reference
+to 1e-10 (rounding spread over the other valid roundings of the reference
 NR) and that take the same substeps and Newton iterations (niter counts
 outer, dust/IR and chemistry iterations, so equal counts mean every
 convergence test came out the same) match to 1e-9
@@ -81,10 +81,11 @@ def test_nr_grid128_subsample():
     _check_nr(sub, dt, 1.0, label="NR grid128 subsample")
 
 
-def test_nr_isothermal_and_evolve_ir():
+def test_nr_isothermal_fixed_and_evolve_ir():
     cells, dt = W.small_cells()
     sub = {k: np.ascontiguousarray(v[:256]) for k, v in cells.items()}
     _check_nr(sub, dt, 1.0, par_over=dict(thermal_mode=1), label="NR isothermal")
+    _check_nr(sub, dt, 1.0, par_over=dict(ir_mode=0), label="NR FIXED IR")
     rng = np.random.default_rng(5)
     tir = 10 ** rng.uniform(np.log10(3.0), np.log10(50.0), 256)
     sub["eir"] = 7.5657e-15 * tir ** 4 / 1e-4

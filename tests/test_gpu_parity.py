@@ -6,7 +6,7 @@ FP64 bar.  The subcycled LI map is ill-conditioned for part of the cells
 the operator-split fixed point): there, rounding alone moves the result by
 more than 1e-9, so no binary64 implementation with a different rounding
 can agree with the reference to 1e-9.  Each cell's rounding spread is
-measured from six other valid roundings of the reference itself
+measured from the other valid roundings of the reference itself
 (contracted multiply-adds with transcendentals nudged up by one ulp;
 transcendentals nudged down with powers formed as exp(y log x); quotients
 through a reciprocal moved one ulp up or down; the input energy moved by
@@ -120,8 +120,17 @@ def test_mixed_full_temperature_range():
     check_mixed_bar(gpu, ref, cells, 3.15576e10, onet, opar, "mixed 1 K - 1e8 K")
 
 
+def test_fp64_fixed_ir():
+    """IR field held at the CMB's (FIXED IR, the Appendix C system without
+    its E_IR row): the closure of an optically thin cell."""
+    cells, dt = W.small_cells()
+    sub = {k: np.ascontiguousarray(v[:1024]) for k, v in cells.items()}
+    _check_fp64(sub, dt, 10.0, par_over=dict(ir_mode=0), label="FIXED IR 1024 cells")
+
+
 def test_fp64_evolve_ir():
-    """IR energy density evolved with the dust (Appendix C 3x3 system)."""
+    """IR energy density evolved with the dust (Appendix C 3x3 system), the
+    IR field drawn over T_IR = 3 - 50 K."""
     cells, dt = W.small_cells()
     sub = {k: np.ascontiguousarray(v[:1024]) for k, v in cells.items()}
     rng = np.random.default_rng(5)
@@ -307,7 +316,7 @@ def test_dispatch_changes_nothing_but_order():
 
 def test_progress_dispatch_modes_bitwise():
     """Suspend / resume restores the whole lane: binary32 assembly, the
-    evolved IR field, isothermal gas with frozen dust, the subcycle cap (a
+    evolved and the fixed IR field, isothermal gas with frozen dust, the subcycle cap (a
     cell suspended past n_sub_max / 2 resumes on the capped step), each
     bitwise equal to index order with a first pass of 8 subcycles."""
     sfc = _sfc()
@@ -319,6 +328,7 @@ def test_progress_dispatch_modes_bitwise():
     iso = {k: np.ascontiguousarray(v[:2048]) for k, v in small.items()}
     cases = [("mixed", cells, dt, sfc.MIXED, 1.0, {}),
              ("evolve ir", ev, dt1, sfc.FP64, 10.0, dict(ir_mode=1)),
+             ("fixed ir", ev, dt1, sfc.FP64, 10.0, dict(ir_mode=0)),
              ("isothermal frozen dust", iso, dt1, sfc.FP64, 1.0, dict(thermal_mode=1, dust_mode=1)),
              ("cap 40", cells, dt, sfc.FP64, 1.0, dict(n_sub_max=40))]
     for name, c, d, prec, fac, over in cases:
@@ -379,14 +389,14 @@ def test_plain_step_graph_replay():
         eager = {k: v.clone() for k, v in t.items()}
         s = torch.cuda.Stream()
         g = torch.cuda.CUDAGraph()
-        for k in ("y_h2", "y_e", "eint", "tdust"):
+        for k in ("y_h2", "y_e", "eint", "tdust", "eir"):
             t[k].copy_(pristine[k])
         torch.cuda.synchronize()
         with torch.cuda.graph(g, stream=s):
             ctx.step(t, dt, prec)
         torch.cuda.synchronize()
         for rep in range(3):
-            for k in ("y_h2", "y_e", "eint", "tdust"):
+            for k in ("y_h2", "y_e", "eint", "tdust", "eir"):
                 t[k].copy_(pristine[k])
             torch.cuda.synchronize()
             print(f"[gpu] graph replay prec={prec}: replay {rep}", flush=True)

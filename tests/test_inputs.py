@@ -113,3 +113,16 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_ir_field_recipe():
+    """Every population carries E_IR for a radiation temperature
+    log-uniform between T_CMB and the dust temperature (E_IR = (c/c~) a
+    T_IR^4)."""
+    for cells in (W.small_cells()[0], W.grid128(n=50_000)[0], W.hii_region(20_000)[0],
+                  W.grid256(n=30_000, side=64)[0]):
+        tir = (cells["eir"] * W.C_RED / W.A_RAD) ** 0.25
+        td = np.maximum(cells["tdust"], W.T_CMB)
+        assert np.all(tir >= W.T_CMB * (1 - 1e-12)) and np.all(tir <= td * (1 + 1e-12))
+        u = np.log(tir / W.T_CMB) / np.log(td / W.T_CMB)
+        assert abs(np.mean(u) - 0.5) < 0.02 and abs(np.mean(u < 0.25) - 0.25) < 0.02

@@ -39,11 +39,11 @@ def iso_params(**kw):
                                  dust_mode=oracle.DUST_FROZEN, **kw)
 
 
-STATE_KEYS = ("nh", "n_euv", "n_fuv", "zmet", "y_h2", "y_e", "eint", "tdust")
+STATE_KEYS = ("nh", "n_euv", "n_fuv", "zmet", "y_h2", "y_e", "eint", "tdust", "eir")
 
 
 def state(o):
-    return {k: o[k] for k in STATE_KEYS}
+    return {k: o[k] for k in STATE_KEYS if k in o}
 
 
 def evolve(cells, times, net, params):
@@ -481,10 +481,19 @@ def _equilibrium_cells():
                      n_fuv=[1e-3, 1e-2, 3e-4])
 
 
+def _fixed_ir(**kw):
+    """Parameters with FIXED IR: the equilibria below are those of grains
+    and gas in the CMB's field; a cell-local E_IR, with no transport to
+    carry the grains' emission away, keeps the energy they radiate and
+    reaches no such equilibrium."""
+    return oracle.default_params(ir_mode=oracle.IR_FIXED, **kw)
+
+
 def _li_equilibrium(cells, params=None, intervals=((1e9, 1), (1e3, 300), (1e2, 1000), (10, 3000))):
     """LI settled at its fixed point for decreasing call intervals: the
     chemistry+energy / dust split leaves an O(interval) offset from the
     exact equilibrium, which shrinks with the interval."""
+    params = params or _fixed_ir()
     res = []
     cur = cells
     for iv, n in intervals:
@@ -501,7 +510,7 @@ def test_steady_state_independent_of_dust_capacity():
     cells = _equilibrium_cells()
     ref = _li_equilibrium(cells)[-1]
     for f in (10, 100, 1000):
-        o = _li_equilibrium(cells, params=oracle.default_params(dust_cap=1e4 * f))[-1]
+        o = _li_equilibrium(cells, params=_fixed_ir(dust_cap=1e4 * f))[-1]
         for k in ("y_h2", "y_e", "tgas", "tdust"):
             np.testing.assert_allclose(o[k], ref[k], rtol=1e-5, err_msg=k)
 
@@ -512,7 +521,7 @@ def test_li_agrees_with_nr_at_equilibrium():
     processes', NR paragraph; both with C_d = 1e4); the LI offset from it is
     first order in the call interval."""
     cells = _equilibrium_cells()
-    for _, nr in evolve_fixed(cells, 1e9 * YR, 4, solver=oracle.nr_step):
+    for _, nr in evolve_fixed(cells, 1e9 * YR, 4, params=_fixed_ir(), solver=oracle.nr_step):
         assert np.all((nr["flags"] & oracle.F_NRFAIL) == 0)
     li = _li_equilibrium(cells, intervals=((1e9, 1), (1e3, 300), (1e2, 1000), (10, 3000),
                                            (1, 10000)))
@@ -586,7 +595,7 @@ def test_collapse_tracks_insensitive_to_dust_capacity():
     from paper_2604_21438_amd import collapse as CO
 
     def track(factor):
-        par = oracle.default_params()
+        par = _fixed_ir()  # optically thin parcel (no IR transport)
         par.dust_cap = 1e4 * factor
         return CO.run(lambda c, dt: oracle.li_step(c, dt, params=par, nthreads=4),
                       CO.initial_parcels())

@@ -182,7 +182,7 @@ def check_steady_state(variant="plain"):
     S_d = 0, and the gas at the grain temperature, T_g = T_d."""
     cells = _coupled_cells(False)
     net = _no_chemistry()
-    par = oracle.default_params(dust_cap=1e4, n_cyc=0, f_chem=1e30)
+    par = oracle.default_params(ir_mode=oracle.IR_FIXED, dust_cap=1e4, n_cyc=0, f_chem=1e30)
     o = oracle.li_step(cells, 1e24, net=net, params=par, variant=variant)
     assert np.all(o["nsub"] == 1) and np.all(o["flags"] & oracle.F_TIGHT)
     np.testing.assert_allclose(o["tgas"], o["tdust"], rtol=1e-9)
