@@ -61,8 +61,10 @@ def kernel_sha1():
     return h.hexdigest()
 
 
-def measured_traffic():
-    if TRAFFIC["kernel_sha1"] is None or TRAFFIC["kernel_sha1"] != kernel_sha1():
+def measured_traffic(n):
+    """The counted bytes, for the full 128^3 step of the sources they were
+    taken on; None for anything else."""
+    if n != 128 ** 3 or TRAFFIC["kernel_sha1"] is None or TRAFFIC["kernel_sha1"] != kernel_sha1():
         return None
     return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
 STATE_KEYS = ("y_h2", "y_e", "eint", "tdust", "eir")
@@ -383,7 +385,7 @@ def gmc_leg(args, sfc, W, torch):
     form: every level submits its next substep as soon as its previous one
     is done (the same device buffers carry the state), so the levels overlap
     on the device; latency per request = done - submit."""
-    levels = W.gmc_levels(target_cells=args.gmc_cells)
+    levels = W.gmc_levels(target_cells=args.gmc_cells, progress=lambda m: log(f"[bench] {m}"))
     nl = len(levels)
     sizes = [lv["cells"]["nh"].shape[0] for lv in levels]
     updates = sum(m * 2 ** L for L, m in enumerate(sizes))
@@ -417,15 +419,19 @@ def gmc_leg(args, sfc, W, torch):
             if prec == sfc.FP64 and not args.gmc_skip_plain:
                 restore()
                 t0 = time.perf_counter()
-                for L in order:
+                for i, L in enumerate(order):
                     ctx.step(bufs[L], levels[L]["dt"], prec)
+                    if args.gmc_cells >= 8_000_000:  # long legs report each level step
+                        torch.cuda.synchronize()
+                        log(f"[bench] gmc plain {pname}: step {i + 1}/{len(order)} (level {L}) "
+                            f"done at {time.perf_counter() - t0:.1f} s")
                 torch.cuda.synchronize()
                 el = time.perf_counter() - t0
                 legs[f"plain_{pname}"] = dict(value=updates / el, seconds=el)
                 log(f"[bench] gmc factor {factor:g} {pname}: plain {el:.2f} s")
             if args.gmc_served in ("both", "copy"):
                 legs.update(gmc_served_copy(ctx, bufs, levels, prec, pname, factor, restore,
-                                            updates))
+                                            updates, verbose=args.gmc_cells >= 8_000_000))
             if args.gmc_served in ("both", "resident"):
                 legs.update(gmc_served_resident(ctx, bufs, levels, prec, pname, factor, restore,
                                                 updates, torch))
@@ -434,7 +440,7 @@ def gmc_leg(args, sfc, W, torch):
     return out
 
 
-def gmc_served_copy(ctx, bufs, levels, prec, pname, factor, restore, updates):
+def gmc_served_copy(ctx, bufs, levels, prec, pname, factor, restore, updates, verbose=False):
     """Served GMC step, every request copied in and out of the arena."""
     nl = len(levels)
     legs = {}
@@ -450,6 +456,9 @@ def gmc_served_copy(ctx, bufs, levels, prec, pname, factor, restore, updates):
                 if r is not None:
                     lat.append(r["t_done"] - r["t_submit"])
                     inflight[L] = None
+                    if verbose:
+                        log(f"[bench] gmc served {pname}: level {L} substep done at "
+                            f"{time.perf_counter() - t0:.1f} s")
             if inflight[L] is None and remaining[L] > 0:
                 inflight[L] = ctx.submit(bufs[L], levels[L]["dt"], prec, level=L,
                                          sync=False)
@@ -606,6 +615,8 @@ def main():
     ap.add_argument("--grid256-sample", type=int, default=65536,
                     help="cells of that leg checked against the CPU reference")
     ap.add_argument("--cells", type=int, default=None, help="fewer cells (testing only)")
+    ap.add_argument("--ir", choices=("evolve", "fixed"), default="evolve",
+                    help="IR mode of the headline step (fixed: the IR field held at the CMB's)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run three device-to-device copies of MIB MiB (a kernel of "
                          "known traffic, to scale the HBM byte counters) and exit")
@@ -677,11 +688,14 @@ def main():
                     subcycles=int(ns.sum()))
 
     # ---- headline: binary64 at dust factor 1 ----
-    ctx = sfc.Context(dust_factor=1.0)
+    evolve = args.ir == "evolve"
+    flop_sub = FLOP_PER_SUBCYCLE if evolve else FLOP_PER_SUBCYCLE_FIXED_IR
+    ctx = sfc.Context(dust_factor=1.0,
+                      params=sfc.default_params(ir_mode=sfc.IR_EVOLVE if evolve else sfc.IR_FIXED))
     step_s, kern_s, out64 = run(ctx, sfc.FP64, args.steps, args.warmup, "fp64 factor 1")
     ctx.close()
     d64 = describe(out64)
-    flops = FLOP_PER_SUBCYCLE * d64["subcycles"]
+    flops = flop_sub * d64["subcycles"]
     achieved = flops / kern_s
     result = {
         "metric": "chem cell-updates/s",
@@ -699,8 +713,9 @@ def main():
         "config": {
             "workload": "grid128: 128^3 = 2,097,152 independent cells, log n_H ~ U[0,8], "
                         "log T ~ U[1,4], T_d = T, Z in {0.01,0.1,1}, dt = 10 kyr, "
-                        "dust factor 1 (C_d = 1e4 erg/g/K), E_IR evolved (T_IR log-uniform "
-                        "in [T_CMB, T_d])",
+                        "dust factor 1 (C_d = 1e4 erg/g/K), " +
+                        ("E_IR evolved (T_IR log-uniform in [T_CMB, T_d])" if evolve
+                         else "IR field held at the CMB's (FIXED)"),
             "cells": n, "dt_s": dt, "dust_factor": 1.0, "precision": "fp64",
             "dispatch": "progress", "phase_nsub": int(sfc.default_params().phase_nsub),
         },
@@ -710,15 +725,15 @@ def main():
             "peak": PEAK_FP64_VALU / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_VALU,
-            "traffic": measured_traffic(),
+            "traffic": measured_traffic(n) if evolve else None,
             "traffic_unit": "bytes per step (both launches)",
-            "algorithmic_bytes": n * BYTES_PER_CELL,
+            "algorithmic_bytes": n * (BYTES_PER_CELL if evolve else BYTES_PER_CELL - 16),
             "kernel": "li_step_kernel<double>",
             "launches_per_step": 2,
-            "flop_per_subcycle": FLOP_PER_SUBCYCLE,
+            "flop_per_subcycle": flop_sub,
             "subcycles_per_step": d64["subcycles"],
             "kernel_s_per_step": kern_s,
-            "hbm_gbs_algorithmic": n * BYTES_PER_CELL / kern_s / 1e9,
+            "hbm_gbs_algorithmic": n * (BYTES_PER_CELL if evolve else BYTES_PER_CELL - 16) / kern_s / 1e9,
         },
         "stats_fp64": d64,
     }

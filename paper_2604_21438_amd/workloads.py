@@ -291,7 +291,8 @@ def _gaussian_field(g, side: int, slope: float = 11.0 / 3.0):
 
 
 def gmc_levels(target_cells: int = 4_000_000, base_side: int = 64, n_levels: int = 6,
-               sigma: float = 2.5, n_sources: int = 64, zmet: float = 0.1, seed_offset: int = 0):
+               sigma: float = 2.5, n_sources: int = 64, zmet: float = 0.1, seed_offset: int = 0,
+               progress=None):
     """A GMC-like AMR hierarchy of 8^3-cell blocks for the served form.
 
     Level 0 covers the unit cube with base_side^3 cells; ln n_H = ln 100 +
@@ -306,7 +307,8 @@ def gmc_levels(target_cells: int = 4_000_000, base_side: int = 64, n_levels: int
     A_s ~ logU[1, 100] cm^-3, r_s ~ logU[1, 10]); Z = zmet.
 
     Returns a list of levels, each a dict with 'cells' (SoA, blocks
-    concatenated), 'dt' = 10 kyr / 2^L, 'blocks' and 'level'."""
+    concatenated), 'dt' = 10 kyr / 2^L, 'blocks' and 'level'.  progress,
+    if given, is called with a line of text after each trial threshold."""
     g = _streams(4, 8, seed_offset)
     base = np.exp(np.log(100.0) + sigma * _gaussian_field(g[0], base_side))
     nb0 = base_side // BLOCK
@@ -320,8 +322,9 @@ def gmc_levels(target_cells: int = 4_000_000, base_side: int = 64, n_levels: int
 
     cap = 4 * target_cells
 
-    def build(n0):
-        """The hierarchy for threshold n0, or None once it exceeds cap cells."""
+    def build(n0, count_only=False):
+        """The hierarchy for threshold n0, or None once it exceeds cap cells
+        (count_only: its cell count, without drawing the finest level)."""
         levels = []
         corners, dens = blocks_of(base, base_side)
         total = 0
@@ -336,6 +339,8 @@ def gmc_levels(target_cells: int = 4_000_000, base_side: int = 64, n_levels: int
                 break
             if total + 8 * int(refine.sum()) * BLOCK ** 3 > cap:
                 return None
+            if count_only and L == n_levels - 2:
+                return total + 8 * int(refine.sum()) * BLOCK ** 3
             pc, pd = corners[refine], dens[refine]
             # each parent block -> 8 children at twice the resolution
             up = pd.repeat(2, axis=1).repeat(2, axis=2).repeat(2, axis=3)  # (m, 16, 16, 16)
@@ -350,22 +355,28 @@ def gmc_levels(target_cells: int = 4_000_000, base_side: int = 64, n_levels: int
             corners, dens = np.concatenate(ch_c), np.concatenate(ch_d)
         return levels
 
+    def count(n0):
+        c = build(n0, count_only=True)
+        return c if isinstance(c, (int, np.integer)) or c is None else sum(d.size for _, d in c)
+
+    # bisection on n0 over counts, then one full build at the chosen threshold
     lo, hi = 1.0, 1.0e12
-    levels = None
+    chosen = None
     for _ in range(80):
         mid = np.sqrt(lo * hi)
-        trial = build(mid)
-        total = cap + 1 if trial is None else sum(d.size for _, d in trial)
-        if trial is not None:
-            levels = trial
+        c = count(mid)
+        total = cap + 1 if c is None else c
+        if progress:
+            progress(f"gmc threshold n0 = {mid:.4g}: {'over the cap' if c is None else int(c)} cells")
+        if c is not None:
+            chosen = mid
         if abs(total - target_cells) <= 0.02 * target_cells:
             break
         if total > target_cells:
             lo = mid
         else:
             hi = mid
-    if levels is None:
-        levels = build(hi)
+    levels = build(chosen if chosen is not None else hi)
     src = g[1].uniform(0.0, 1.0, (n_sources, 3))
     amp = 10.0 ** g[2].uniform(0.0, 2.0, n_sources)
     ratio = 10.0 ** g[3].uniform(0.0, 1.0, n_sources)
