@@ -822,10 +822,47 @@ __device__ inline void kappa(const Net& nt, R T, R& k, R& dk) {
   dk = R(nt.kap_max) * R(2) * x * id * id * R(nt.kap_tn);
 }
 
-// Appendix C sources and coefficients at (T_g, T_d, E_IR)
+// Appendix C terms that depend on (T_d, E_IR) alone: grain emission and
+// IR absorption with their logarithmic derivatives.  The chemistry solve
+// of a subcycle leaves T_d and E_IR as they were, so a subcycle takes
+// these once for its timescale and its dust solve.
 template <class R>
-__device__ inline void dust_eval(const Net& nt, const Par& pr, double Tg_, double Td_,
-                                 double Eir_, const CellK& ck, Dust<R>& d) {
+struct DustRad {
+  R betad, absir, betair, emis, kir;
+};
+
+template <class R>
+__device__ inline void dust_rad(const Net& nt, const Par& pr, double Td_, double Eir_,
+                                DustRad<R>& r) {
+  using M = Mth<R>;
+  const R Td = R(Td_);
+  R kd, dkd;
+  kappa<R>(nt, Td, kd, dkd);
+  r.betad = R(4) * kd + dkd * Td;
+  const R ctil = R(pr.c_red * CL);
+  if (pr.ir_mode == 1) {
+    const R E = R(Eir_);
+    const R tir = M::sq(M::sq(R(pr.cr_a) * E));
+    R ki, dki;
+    kappa<R>(nt, tir, ki, dki);
+    r.kir = ki;
+    r.absir = ki * ctil * E;
+    r.betair = ki + dki * tir * R(0.25);
+  } else {
+    // FIXED: T_IR = T_CMB, constants of the call
+    r.kir = R(pr.kir_fix);
+    r.absir = R(pr.absir_fix);
+    r.betair = R(pr.betair_fix);
+  }
+  const R td2 = Td * Td;
+  r.emis = kd * R(ARAD * CL) * td2 * td2;
+}
+
+// Appendix C sources and coefficients at (T_g, T_d, E_IR), the radiative
+// terms of (T_d, E_IR) given
+template <class R>
+__device__ inline void dust_gas(const Net& nt, double Tg_, double Td_, const CellK& ck,
+                                const DustRad<R>& r, Dust<R>& d) {
   using M = Mth<R>;
   const R Tg = R(Tg_), Td = R(Td_);
   const R iTg = M::dv(R(1), Tg);
@@ -833,30 +870,23 @@ __device__ inline void dust_eval(const Net& nt, const Par& pr, double Tg_, doubl
   d.gd = R(1) - R(0.8) * M::ea(-TLOW * frcp(Tg_));
   const R rr = Td * iTg - R(1);
   d.zeta = R(0.5) * d.gd * rr + (d.gd - R(1)) * R(TLOW) * iTg * rr - d.gd;
-  R kd, dkd;
-  kappa<R>(nt, Td, kd, dkd);
-  d.betad = R(4) * kd + dkd * Td;
-  const R ctil = R(pr.c_red * CL);
-  if (pr.ir_mode == 1) {
-    const R E = R(Eir_);
-    const R tir = M::sq(M::sq(R(pr.cr_a) * E));
-    R ki, dki;
-    kappa<R>(nt, tir, ki, dki);
-    d.kir = ki;
-    d.absir = ki * ctil * E;
-    d.betair = ki + dki * tir * R(0.25);
-  } else {
-    // FIXED: T_IR = T_CMB, constants of the call
-    d.kir = R(pr.kir_fix);
-    d.absir = R(pr.absir_fix);
-    d.betair = R(pr.betair_fix);
-  }
-  const R td2 = Td * Td;
-  d.emis = kd * R(ARAD * CL) * td2 * td2;
+  d.betad = r.betad;
+  d.kir = r.kir;
+  d.absir = r.absir;
+  d.betair = r.betair;
+  d.emis = r.emis;
   const R coup = d.G * d.gd * (Td - Tg);
   d.Sd = d.absir + R(ck.euv) - d.emis - coup;
   d.Sir = R(ck.rho * ck.fd) * (d.emis - d.absir);
   d.Sg = R(ck.fd) * coup;
+}
+
+template <class R>
+__device__ inline void dust_eval(const Net& nt, const Par& pr, double Tg_, double Td_,
+                                 double Eir_, const CellK& ck, Dust<R>& d) {
+  DustRad<R> r;
+  dust_rad<R>(nt, pr, Td_, Eir_, r);
+  dust_gas<R>(nt, Tg_, Td_, ck, r, d);
 }
 
 // ------------------------------------------------------------------ LU
@@ -1020,12 +1050,13 @@ __device__ inline void tight_phi(const Net& nt, const Par& pr, const TightC& t, 
 // kappa(T_IR) frozen; T_g and E_IR are explicit in T_d, leaving one
 // increasing convex equation Phi(T_d) = 0.
 template <class R>
-__device__ inline void dust_tight(const Net& nt, const Par& pr, Lane& L, double h) {
+__device__ inline void dust_tight(const Net& nt, const Par& pr, Lane& L, double h,
+                                  const DustRad<double>& rad) {
   const double knb = KB * L.ck.n;
   const double cv = knb * cvk(pr, L.y2, L.ye);
   const double Tg0 = L.E * frcp(cv);
   Dust<double> d;
-  dust_eval<double>(nt, pr, Tg0, L.Td, L.Eir, L.ck, d);
+  dust_gas<double>(nt, Tg0, L.Td, L.ck, rad, d);
   TightC t;
   t.td0 = L.Td;
   t.tg0 = Tg0;
@@ -1098,12 +1129,13 @@ __device__ inline void dust_tight(const Net& nt, const Par& pr, Lane& L, double 
 
 // One Appendix C linear solve over h, rows and columns scaled.
 template <class R>
-__device__ inline void dust_linear(const Net& nt, const Par& pr, Lane& L, double h) {
+__device__ inline void dust_linear(const Net& nt, const Par& pr, Lane& L, double h,
+                                   const DustRad<double>& rad) {
   const double knb = KB * L.ck.n;
   const double cv = knb * cvk(pr, L.y2, L.ye);
   const double Tg = L.E * frcp(cv);
   Dust<double> d;
-  dust_eval<double>(nt, pr, Tg, L.Td, L.Eir, L.ck, d);
+  dust_gas<double>(nt, Tg, L.Td, L.ck, rad, d);
   const double ctil = pr.c_red * CL;
   const double ac = ARAD * CL;
   const double G = double(d.G), gd = double(d.gd), zeta = double(d.zeta);
@@ -1169,9 +1201,11 @@ __device__ bool subcycle(const Net& nt, const Par& pr, Lane& L) {
   const double f0 = double(ch.f[0]), f1 = double(ch.f[1]), fq = double(ch.f[2]);
 
   double nu_dust = 0.0, qgg = 0.0;
+  DustRad<double> rad;
   if (dust_on) {
+    dust_rad<double>(nt, pr, L.Td, L.Eir, rad);
     Dust<double> d;
-    dust_eval<double>(nt, pr, T, L.Td, L.Eir, L.ck, d);
+    dust_gas<double>(nt, T, L.Td, L.ck, rad, d);
     // gas-grain exchange rho S_g / (k_B n) [K/s]
     qgg = double(d.Sg) * (L.ck.rho / knb);
     const double alpha = knb * (ntr * pr.igm1) * frcp(L.ck.rho);
@@ -1243,8 +1277,8 @@ __device__ bool subcycle(const Net& nt, const Par& pr, Lane& L) {
   renormalise<R>(nt, pr, L, iso);
 
   if (dust_on) {
-    if (!tight) dust_linear<R>(nt, pr, L, h);
-    else dust_tight<R>(nt, pr, L, h);
+    if (!tight) dust_linear<R>(nt, pr, L, h, rad);
+    else dust_tight<R>(nt, pr, L, h, rad);
     dust_floors(pr, L);
   }
   L.nsub += 1;
