@@ -139,7 +139,9 @@ typedef struct {
   int32_t phase_nsub;  /* PROGRESS: subcycles of the first pass, >= 1 [4096] */
   int32_t photon_absorb; /* 1: after the update, the EUV and FUV photon
                           densities absorbed over dt are written to
-                          sfc_cells.n_euv_out / n_fuv_out (plain path):
+                          sfc_cells.n_euv_out / n_fuv_out (plain path and
+                          served form; the served arena then holds two more
+                          float64 arrays, 16 B per cell):
                           N exp(-c~ alpha dt), alpha_EUV = sigma_EUV n_H y_H
                           + kappa_UV rho Z, alpha_FUV = kappa_UV rho Z, with
                           the updated y_H (Sec. 2 "Radiation components")

@@ -195,13 +195,16 @@ __device__ inline void set_level_prio(int lvl, int& prio) {
 // from the host at each wave's start, is larger), waves stop claiming and
 // leave when their lanes are done (each cell is bounded by n_sub_max
 // subcycles), so every wave reaches an exit and the newer launch, whose
-// waves take the freed slots, serves all new work.
+// waves take the freed slots, serves all new work.  An exiting wave raises
+// its slot's left word, which tells the host that the launch has begun to
+// shrink.
 template <class R, bool kS>
 __global__ __launch_bounds__(kBlock) void served_drain_kernel(ServedArgs) {
   stage_tables();
   const int lane = threadIdx.x & 63;
   int64_t cell = -1;
   uint64_t tk = 0, pend = 0;  // the lane's request token; pend = tk + 1 once stored
+  double cdt = 0.0;           // the lane's request dt (photon absorption at the store)
   Lane L;
   WaveCache wc;
   const uint64_t t0 = (uint64_t)wall_clock64();
@@ -253,6 +256,7 @@ __global__ __launch_bounds__(kBlock) void served_drain_kernel(ServedArgs) {
         if (r < unsigned(c.take)) {
           cell = int64_t(c.off + c.first + r);
           tk = c.tk;
+          cdt = c.dt;
           if (!load_cell<R>(fresh(a.netc), fresh(a.parc), a.arena, cell, c.dt, L)) {
             cell = -1;
             pend = tk + 1;
@@ -270,13 +274,18 @@ __global__ __launch_bounds__(kBlock) void served_drain_kernel(ServedArgs) {
     if (a.level_prio) set_level_prio(cell >= 0 ? int((tk >> kLevelShift) & 0xff) : -1, prio);
     if (cell >= 0) {
       if (subcycle<R, kS>(fresh(a.netc), fresh(a.parc), L)) {
-        store_cell<R>(fresh(a.netc), fresh(a.parc), a.arena, cell, L);
+        store_cell<R>(fresh(a.netc), fresh(a.parc), a.arena, cell, L, cdt);
         cell = -1;
         pend = tk + 1;
       }
     }
   }
   if (__ballot(pend != 0)) flush_done(kargs<ServedArgs>(), pend);
+  // tell the host that this launch no longer holds all its waves
+  if (lane == 0) {
+    const ServedArgs& a = kargs<ServedArgs>();
+    __hip_atomic_store(a.left + a.slot, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
 }
 
 __global__ __launch_bounds__(256) void copy_in_kernel(CopyArgs a) {
@@ -315,6 +324,8 @@ __global__ __launch_bounds__(256) void copy_out_kernel(CopyArgs a) {
     if (a.user.nsub) a.user.nsub[i] = a.arena.nsub[j];
     if (a.user.niter) a.user.niter[i] = a.arena.niter[j];
     if (a.user.flags) a.user.flags[i] = a.arena.flags[j];
+    if (a.user.n_euv_out && a.arena.n_euv_out) a.user.n_euv_out[i] = a.arena.n_euv_out[j];
+    if (a.user.n_fuv_out && a.arena.n_fuv_out) a.user.n_fuv_out[i] = a.arena.n_fuv_out[j];
   }
 }
 

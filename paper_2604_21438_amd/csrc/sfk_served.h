@@ -43,6 +43,7 @@ struct ServedArgs {
   const unsigned long long* staged;   // device, kClasses: requests armed
   unsigned long long* newest;         // device: largest launch generation started (this precision)
   const uint64_t* gen;                // host-mapped, per drain slot: generation of its latest launch
+  uint64_t* left;                     // host-mapped, per drain slot: 1 once a wave of its latest launch has exited
   uint64_t* done;                     // host-mapped, per ring slot: seq + 1 when complete
   uint64_t ring;                      // slots per class, a power of two
   uint64_t idle_ticks;                // a wave with no work for this long exits

@@ -83,9 +83,10 @@ double env_num(const char* name, double dflt) {
   return (end && *end == 0) ? x : dflt;
 }
 
-int64_t cell_bytes(bool evolve) {
-  // 12 float64 arrays (13 with E_IR) and 3 int32 arrays per arena cell
-  return 8 * (evolve ? 13 : 12) + 4 * 3;
+int64_t cell_bytes(bool evolve, bool absorb) {
+  // 12 float64 arrays (one more with E_IR, two more with the absorbed
+  // photon densities) and 3 int32 arrays per arena cell
+  return 8 * (12 + (evolve ? 1 : 0) + (absorb ? 2 : 0)) + 4 * 3;
 }
 
 }  // namespace
@@ -105,7 +106,11 @@ struct Server : sfsched::Ops {
   // the freed slots, so newly published requests find a full complement of
   // waves instead of the few survivors.  Once the newer kernel's waves
   // start, the older kernel's waves stop claiming and leave as their cells
-  // finish, so its slot frees up for the next launch.
+  // finish, so its slot frees up for the next launch.  The second kernel is
+  // launched only once a wave of the live one has exited: while the live
+  // kernel holds all its waves they claim the new requests themselves, and
+  // a handover then would stop them claiming while the newer kernel's waves
+  // wait for room behind their long cells.
   hipStream_t drain_stream[2] = {nullptr, nullptr};
   hipEvent_t drain_ev[2] = {nullptr, nullptr};
   bool drain_live[2] = {false, false};
@@ -113,6 +118,8 @@ struct Server : sfsched::Ops {
   uint64_t drain_pub[2] = {0, 0};  // requests of its precision published at its launch
   uint64_t* gen = nullptr;         // coherent pinned host memory, per slot: latest launch generation
   uint64_t* d_gen = nullptr;
+  uint64_t* left = nullptr;        // same allocation, per slot: a wave of its latest launch has exited
+  uint64_t* d_left = nullptr;
   uint64_t gen_count = 0;
   int last_prec = 1;
   std::vector<hipEvent_t> events;  // pool
@@ -144,6 +151,8 @@ struct Server : sfsched::Ops {
     a.user.nsub = c.nsub;
     a.user.niter = c.niter;
     a.user.flags = c.flags;
+    a.user.n_euv_out = c.n_euv_out;
+    a.user.n_fuv_out = c.n_fuv_out;
     a.arena = arena;
     a.off = r.off;
     a.z_default = cfg.par.z_default;
@@ -251,11 +260,15 @@ struct Server : sfsched::Ops {
       }
       if (pick < 0 && drain_live[o]) {
         const int p = drain_prec[o];
-        if (core->running(p) > 0 && core->published_total(p) > drain_pub[o]) pick = p;
+        if (core->running(p) > 0 && core->published_total(p) > drain_pub[o] &&
+            __atomic_load_n(left + o, __ATOMIC_ACQUIRE) != 0)
+          pick = p;
       }
       if (pick < 0) continue;
       // a launch's waves read its generation when they start; older waves of
-      // the same precision stop claiming once a newer launch has started
+      // the same precision stop claiming once a newer launch has started.
+      // The slot's previous kernel has ended, so nothing writes its left word.
+      __atomic_store_n(left + i, uint64_t(0), __ATOMIC_RELEASE);
       __atomic_store_n(gen + i, ++gen_count, __ATOMIC_RELEASE);
       hipError_t e = hipGraphLaunch(q[pick].exec[i], drain_stream[i]);
       if (e == hipSuccess) e = hipEventRecord(drain_ev[i], drain_stream[i]);
@@ -343,13 +356,14 @@ Server* create(const Config& cfg, std::string* err, int* code) {
   if (!s) return fail(nullptr, SFC_E_NOMEM, "server allocation");
   s->cfg = cfg;
   s->evolve = cfg.par.ir_mode == 1;
+  const bool absorb = cfg.par.photon_absorb == 1;
   s->ring = env_ring();
-  const int64_t cb = cell_bytes(s->evolve);
+  const int64_t cb = cell_bytes(s->evolve, absorb);
   s->cap = int64_t(cfg.budget_bytes / uint64_t(cb));
   s->cap = (s->cap / 64) * 64;
   if (s->cap < 64) return fail(s, SFC_E_INVAL, "served budget below 64 cells");
   // arena: one allocation, each array 256-byte aligned
-  const int64_t nd = s->evolve ? 13 : 12;
+  const int64_t nd = 12 + (s->evolve ? 1 : 0) + (absorb ? 2 : 0);
   const int64_t dbytes = ((s->cap * 8 + 255) / 256) * 256;
   const int64_t ibytes = ((s->cap * 4 + 255) / 256) * 256;
   if (hipMalloc(&s->arena_mem, size_t(nd * dbytes + 3 * ibytes)) != hipSuccess)
@@ -380,6 +394,8 @@ Server* create(const Config& cfg, std::string* err, int* code) {
   A.n_euv = dnext();
   A.n_fuv = dnext();
   A.zmet = dnext();
+  A.n_euv_out = absorb ? dnext() : nullptr;
+  A.n_fuv_out = absorb ? dnext() : nullptr;
   A.nsub = inext();
   A.niter = inext();
   A.flags = reinterpret_cast<uint32_t*>(inext());
@@ -408,6 +424,8 @@ Server* create(const Config& cfg, std::string* err, int* code) {
     std::memset(s->gen, 0, 256);
     if (hipHostGetDevicePointer(reinterpret_cast<void**>(&s->d_gen), s->gen, 0) != hipSuccess)
       return fail(s, SFC_E_DEVICE, "host pointer mapping");
+    s->left = s->gen + 8;  // its own 64-byte line of the 256-byte block
+    s->d_left = s->d_gen + 8;
   }
 
   int khz = 0;
@@ -458,6 +476,7 @@ Server* create(const Config& cfg, std::string* err, int* code) {
     a.staged = q.ctr + 2 * sfk::kClasses;
     a.newest = q.ctr + 3 * sfk::kClasses;
     a.gen = s->d_gen;
+    a.left = s->d_left;
     a.done = q.d_done;
     a.ring = s->ring;
     a.idle_ticks = uint64_t(env_num("SFC_SERVE_IDLE_MS", 100.0) * 1e-3 * tps);

@@ -136,3 +136,58 @@ def test_mixed_with_every_piece_on():
     print(f"[gpu f2] mixed: median {np.median(w):.2e} p99 {np.percentile(w, 99):.2e} "
           f"max {w.max():.2e}", flush=True)
     assert np.median(w) <= 1e-6
+
+
+def test_served_photon_absorption_matches_plain():
+    """The served form applies the same absorption at the store: for each
+    request the photon densities after the step (and every other output)
+    are bitwise the plain step's, in both precisions, and a second context
+    without photon_absorb leaves the output buffers untouched."""
+    import torch
+    import paper_2604_21438_amd as sfc
+    net = sfc.default_network(shield_mode=1, pe_mode=1)
+    par = sfc.default_params(photon_absorb=1)
+    reqs = []
+    for j, (n, dt) in enumerate(((700, 3.15576e11), (333, 3.15576e11 / 4), (1024, 3.15576e10))):
+        cells, _ = _population(n, 20 + j)
+        cells["nh"][j] = -1.0  # an invalid cell keeps its photons
+        reqs.append((cells, dt))
+    keys = ("y_h2", "y_e", "eint", "tdust", "eir", "y_h", "y_hp", "y_hm", "tgas", "nsub",
+            "niter", "flags", "n_euv_out", "n_fuv_out")
+    ctx = sfc.Context(network=net, params=par, served_budget_bytes=32 << 20)
+    try:
+        for prec in (sfc.FP64, sfc.MIXED):
+            print(f"[gpu f2] served photon absorption prec={prec}: {len(reqs)} requests", flush=True)
+            bufs = [sfc.to_device(c, photons=True) for c, _ in reqs]
+            torch.cuda.synchronize()
+            tickets = [ctx.submit(b, dt, prec, level=i, tag=i)
+                       for i, (b, (_, dt)) in enumerate(zip(bufs, reqs))]
+            ctx.drain()
+            for tk in tickets:
+                assert ctx.poll(tk)["status"] == 0
+            for i, (b, (c, dt)) in enumerate(zip(bufs, reqs)):
+                t = sfc.to_device(c, photons=True)
+                ctx.step(t, dt, prec)
+                torch.cuda.synchronize()
+                for k in keys:
+                    x, y = b[k].cpu().numpy(), t[k].cpu().numpy()
+                    same = x.view(np.int64) == y.view(np.int64) if x.dtype.kind == "f" else x == y
+                    assert same.all(), (prec, i, k, int((~same).sum()))
+                out = b["n_euv_out"].cpu().numpy()
+                assert out[i] == c["n_euv"][i] and np.all(out <= c["n_euv"])
+                assert np.any(out < c["n_euv"])
+    finally:
+        ctx.close()
+    # without photon_absorb the served form does not touch the photon outputs
+    ctx = sfc.Context(network=net, params=sfc.default_params(), served_budget_bytes=32 << 20)
+    try:
+        c, dt = reqs[0]
+        b = sfc.to_device(c, photons=True)
+        b["n_euv_out"].fill_(-7.0)
+        torch.cuda.synchronize()
+        tk = ctx.submit(b, dt, sfc.FP64, level=0, tag=0)
+        ctx.drain()
+        assert ctx.poll(tk)["status"] == 0
+        assert np.all(b["n_euv_out"].cpu().numpy() == -7.0)
+    finally:
+        ctx.close()
