@@ -33,9 +33,10 @@ sys.path.insert(0, ROOT)
 # sqrt with a multiply-add counted as 2, plus 44 transcendental calls counted
 # as 1 each, and the tight dust solve's Newton iterations), from the counting
 # build of the CPU reference on a seeded sample of this workload with E_IR
-# evolved: python -m oracle.count_ops; with the IR field held (FIXED), 1539
-FLOP_PER_SUBCYCLE = 1695.0
-FLOP_PER_SUBCYCLE_FIXED_IR = 1539.0
+# evolved: python -m oracle.count_ops; with the IR field held (FIXED):
+# python -m oracle.count_ops --fixed-ir
+FLOP_PER_SUBCYCLE = 1705.0
+FLOP_PER_SUBCYCLE_FIXED_IR = 1552.0
 PEAK_FP64_VALU = 78.6e12      # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 BYTES_PER_CELL = 148          # 9 float64 reads, 8 float64 writes, 3 int32 writes (E_IR evolved)
 # HBM bytes of one binary64 step on the 128^3 workload (the two launches of

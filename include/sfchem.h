@@ -62,8 +62,9 @@ typedef enum { SFC_DUST_EVOLVE = 0, SFC_DUST_FROZEN = 1 } sfc_dust_mode;
  *             then is suspended (its state written back in place, the rest
  *             of it kept by the context).  The second resumes the suspended
  *             cells, longest estimated remainder first, the estimate being
- *             the subcycles still needed at the cell's pace so far.  Cells
- *             that cost ~1e5 subcycles then start first instead of wherever
+ *             the subcycles still needed at the larger of the cell's average
+ *             pace so far and the pace of its last subcycle.  Cells that
+ *             cost ~1e5 subcycles then start first instead of wherever
  *             density puts them.  Uses 36 B of context-owned device memory
  *             per cell (allocated at the first call that needs more).
  *   NR comparator calls (sfc_chem_step_nr) use DENSITY under PROGRESS. */

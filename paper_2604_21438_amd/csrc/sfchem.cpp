@@ -557,8 +557,7 @@ int step_launch(sfc_ctx* ctx, const sfc_cells* cells, double dt, int method, voi
   if (e != hipSuccess) return hip_fail(ctx, e, "step launch");
   if (progress) {
     // second pass: the suspended cells, longest estimated remainder first
-    e = sfk::launch_progress_order(a.sus, dt, ctx->par.n_sub_max, buf.sus_cap, buf.buckets,
-                                   buf.order, s);
+    e = sfk::launch_progress_order(a.sus, buf.sus_cap, buf.buckets, buf.order, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "progress order launch");
     sfk::Args b = a;
     b.budget = 0;

@@ -69,7 +69,7 @@ struct Suspended {
   double *rem, *tiso;         // remaining time of the interval, isothermal T
   int32_t *nsub, *nit;        // counters so far
   uint32_t* fl;               // flags so far
-  int32_t* bucket;            // scratch: estimated-cost bucket per slot
+  int32_t* bucket;            // estimated-cost bucket per slot, written at suspension
 };
 
 struct Args {
@@ -116,9 +116,10 @@ constexpr int kOrderDenseWord = 2 * kOrderBuckets + 1;  // plan[1]: length of th
 hipError_t launch_order(const double* nh, int64_t n, bool all_dense, int32_t* order,
                         uint32_t* work, hipStream_t s);
 // Two-phase dispatch, second phase: order[0..*sus.count) = the suspended
-// slots, longest estimated remainder first (cap = slot capacity).
-hipError_t launch_progress_order(const Suspended& sus, double dt, int32_t n_sub_max,
-                                 int64_t cap, uint32_t* work, int32_t* order, hipStream_t s);
+// slots, longest estimated remainder first (cap = slot capacity; each
+// slot's cost bucket was written when its cell was suspended).
+hipError_t launch_progress_order(const Suspended& sus, int64_t cap, uint32_t* work,
+                                 int32_t* order, hipStream_t s);
 
 constexpr int kBlock = 256;
 

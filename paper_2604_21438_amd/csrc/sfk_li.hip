@@ -19,6 +19,27 @@ namespace {
 // the L2 of the XCD the wave runs on.
 constexpr unsigned kStash = 64;
 
+// Estimated cost bucket of a cell suspended after its first pass: the
+// subcycles it still needs at the larger of two paces, the average over
+// the pass (nsub steps covered dt - rem) and that of its last subcycle
+// (hlast), at most what the subcycle cap leaves; half-octave buckets.
+// The last step catches cells whose steps have begun to shrink: at the
+// average pace they would be claimed last and run alone at the end.
+__device__ inline int progress_bucket(double dt, double rem, int32_t nsub, int32_t nmax,
+                                      double hlast) {
+  double est = double(nmax - nsub);
+  const double done = dt - rem;
+  if (done > 0.0) {
+    double g = double(nsub) * (rem / done);
+    if (hlast > 0.0) g = fmax(g, rem / hlast);
+    if (g < est) est = g;
+  }
+  if (!(est > 0.0)) est = 0.0;
+  const float l2 = __builtin_amdgcn_logf(float(est) + 1.0f);  // log2
+  const int b = int(floorf(2.0f * l2));
+  return b < 0 ? 0 : (b >= kOrderBuckets ? kOrderBuckets - 1 : b);
+}
+
 // kNR selects the Newton-Raphson comparator instead of the LI subcycle
 // (binary64 only); both share the lane refill, stash and dispatch.
 template <class R, bool kNR, bool kS>
@@ -80,6 +101,7 @@ __device__ __attribute__((always_inline)) inline void step_loop() {
     }
     if (busy == 0) break;
     if (cell >= 0) {
+      const double rem_before = L.rem;
       const bool done = kNR ? nr_attempt<kS>(fresh(a.netc), fresh(a.parc), L, tsub, lev, attempts)
                             : subcycle<R, kS>(fresh(a.netc), fresh(a.parc), L);
       if (done) {
@@ -92,7 +114,10 @@ __device__ __attribute__((always_inline)) inline void step_loop() {
         unsigned long long base = 0;
         if (lane == leader) base = atomicAdd(a.sus.count, (unsigned long long)__popcll(m));
         base = __shfl(base, leader);
-        suspend_cell(fresh(a.parc), a.c, a.sus, cell, base + lanes_below(m), L);
+        const unsigned long long slot = base + lanes_below(m);
+        suspend_cell(fresh(a.parc), a.c, a.sus, cell, slot, L);
+        a.sus.bucket[slot] =
+            progress_bucket(a.dt, L.rem, L.nsub, fresh(a.parc).n_sub_max, rem_before - L.rem);
         cell = -1;
       }
     }
@@ -263,24 +288,10 @@ __global__ __launch_bounds__(256) void order_scatter_kernel(const double* nh, in
 }
 
 // Second phase of two-phase dispatch: the suspended cells, longest
-// estimated remainder first.  The estimate is the subcycles a cell still
-// needs if it keeps the average pace of its first pass, at most what the
-// subcycle cap leaves; cells go in decreasing half-octave buckets of it
-// (any order inside a bucket).  Slots [0, *count) are split into one
-// contiguous share per block.
-__device__ inline int progress_bucket(double dt, double rem, int32_t nsub, int32_t nmax) {
-  double est = double(nmax - nsub);
-  const double done = dt - rem;
-  if (done > 0.0) {
-    const double lin = double(nsub) * (rem / done);
-    if (lin < est) est = lin;
-  }
-  if (!(est > 0.0)) est = 0.0;
-  const float l2 = __builtin_amdgcn_logf(float(est) + 1.0f);  // log2
-  const int b = int(floorf(2.0f * l2));
-  return b < 0 ? 0 : (b >= kOrderBuckets ? kOrderBuckets - 1 : b);
-}
-
+// estimated remainder first, in decreasing half-octave buckets of the
+// estimate (any order inside a bucket), the bucket taken at suspension
+// (progress_bucket).  Slots [0, *count) are split into one contiguous
+// share per block.
 __device__ inline void slot_share(unsigned long long used, int b, int nb, int64_t& begin,
                                   int64_t& end) {
   const int64_t per = (int64_t(used) + nb - 1) / nb;
@@ -289,18 +300,13 @@ __device__ inline void slot_share(unsigned long long used, int b, int nb, int64_
   if (begin > end) begin = end;
 }
 
-__global__ __launch_bounds__(256) void progress_count_kernel(Suspended sus, double dt,
-                                                             int32_t nmax, uint32_t* work) {
+__global__ __launch_bounds__(256) void progress_count_kernel(Suspended sus, uint32_t* work) {
   __shared__ uint32_t h[kOrderBuckets];
   for (int t = threadIdx.x; t < kOrderBuckets; t += blockDim.x) h[t] = 0u;
   __syncthreads();
   int64_t begin, end;
   slot_share(*sus.count, blockIdx.x, gridDim.x, begin, end);
-  for (int64_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
-    const int b = progress_bucket(dt, sus.rem[i], sus.nsub[i], nmax);
-    sus.bucket[i] = b;
-    atomicAdd(&h[b], 1u);
-  }
+  for (int64_t i = begin + threadIdx.x; i < end; i += blockDim.x) atomicAdd(&h[sus.bucket[i]], 1u);
   __syncthreads();
   const OrderWork w = order_work(work);
   for (int t = threadIdx.x; t < kOrderBuckets; t += blockDim.x)
@@ -401,12 +407,12 @@ hipError_t launch_order(const double* nh, int64_t n, bool all_dense, int32_t* or
   return hipGetLastError();
 }
 
-hipError_t launch_progress_order(const Suspended& sus, double dt, int32_t n_sub_max,
-                                 int64_t cap, uint32_t* work, int32_t* order, hipStream_t s) {
+hipError_t launch_progress_order(const Suspended& sus, int64_t cap, uint32_t* work,
+                                 int32_t* order, hipStream_t s) {
   const int64_t tiles = (cap + 255) / 256;
   const int grid = int(tiles < kOrderBlocks ? (tiles > 0 ? tiles : 1) : kOrderBlocks);
   hipLaunchKernelGGL(order_zero_kernel, dim3(1), dim3(256), 0, s, work);
-  hipLaunchKernelGGL(progress_count_kernel, dim3(grid), dim3(256), 0, s, sus, dt, n_sub_max, work);
+  hipLaunchKernelGGL(progress_count_kernel, dim3(grid), dim3(256), 0, s, sus, work);
   hipLaunchKernelGGL(progress_plan_kernel, dim3(1), dim3(64), 0, s, work);
   hipLaunchKernelGGL(progress_scatter_kernel, dim3(grid), dim3(256), 0, s, sus, work, order);
   return hipGetLastError();
