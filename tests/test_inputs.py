@@ -126,3 +126,17 @@ def test_ir_field_recipe():
         assert np.all(tir >= W.T_CMB * (1 - 1e-12)) and np.all(tir <= td * (1 + 1e-12))
         u = np.log(tir / W.T_CMB) / np.log(td / W.T_CMB)
         assert abs(np.mean(u) - 0.5) < 0.02 and abs(np.mean(u < 0.25) - 0.25) < 0.02
+
+
+def test_bench_traffic_only_for_the_counted_step():
+    """The HBM bytes bench.py reports were counted on the full 128^3 step of
+    the plain-step sources whose hash they carry: any other cell count, or
+    a changed source, reports null instead of a stale figure."""
+    sys.path.insert(0, ROOT)
+    import bench
+    full = 128 ** 3
+    ok = bench.kernel_sha1() == bench.TRAFFIC["kernel_sha1"]
+    got = bench.measured_traffic(full)
+    assert (got == bench.TRAFFIC["fetch_bytes"] + bench.TRAFFIC["write_bytes"]) if ok else got is None
+    assert bench.measured_traffic(65536) is None
+    assert bench.measured_traffic(full - 1) is None
