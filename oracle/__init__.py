@@ -52,6 +52,10 @@ LIB_C32 = os.path.join(HERE, "liborc_c32.so")
 # rounded to binary32 before the solve, everything else binary64: the
 # rounding of the mixed path's binary32 partials (mixed-precision bar)
 LIB_J32 = os.path.join(HERE, "liborc_j32.so")
+# the subcycle's Lie split in the other order (Appendix C step first, then
+# chemistry + energy at the updated state): a study of the split order, not
+# another rounding
+LIB_DF = os.path.join(HERE, "liborc_df.so")
 SRC = os.path.join(HERE, "orc_chem.cpp")
 
 NREAC, NPROC, NLINE = 12, 14, 5
@@ -72,7 +76,8 @@ def build(force: bool = True) -> None:
                 (LIB_RCP, ["-DORC_RCP", "-mfma", "-ffp-contract=fast"]),
                 (LIB_RCPDN, ["-DORC_RCP", "-DORC_NUDGE_DOWN"]),
                 (LIB_ALL, ["-DORC_RCP", "-DORC_NUDGE", "-mfma", "-ffp-contract=fast"]),
-                (LIB_C32, ["-DORC_COEF32"]), (LIB_J32, ["-DORC_JAC32"]))
+                (LIB_C32, ["-DORC_COEF32"]), (LIB_J32, ["-DORC_JAC32"]),
+                (LIB_DF, ["-DORC_DUST_FIRST"]))
     for out, extra in variants:
         if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(SRC):
             continue
@@ -141,7 +146,7 @@ def _lib(counting: bool = False, variant: str = "plain"):
     else:
         path = LIB_COUNT if counting else {"fma": LIB_FMA, "dn": LIB_DN, "rcp": LIB_RCP,
                                        "rcpdn": LIB_RCPDN, "all": LIB_ALL,
-                                       "c32": LIB_C32, "j32": LIB_J32}.get(variant, LIB)
+                                       "c32": LIB_C32, "j32": LIB_J32, "df": LIB_DF}.get(variant, LIB)
     if path not in _libs:
         if variant.endswith(".so"):
             if not os.path.exists(path):

@@ -1028,6 +1028,26 @@ static void li_cell(const orc_network& net, const orc_params& p, const orc_cells
       }
     }
 
+#ifdef ORC_DUST_FIRST
+    /* measurement build (split-order study): the same Lie split in the
+     * other order, the Appendix C step over h first, then the chemistry +
+     * energy step with its coefficients taken again at the updated state */
+    if (dust_on) {
+      if (!tight) {
+        dust_linear_step(net, p, c, s, h);
+      } else {
+        bool conv, floored;
+        nit += dust_tight_step(net, p, c, s, h, conv, floored);
+        if (!conv) fl |= ORC_F_NOCONV;
+        if (floored) fl |= ORC_F_FLOOR;
+      }
+      fl |= dust_floors(p, c, s);
+      nt = ntot_rel(p, s.y2, s.ye);
+      cv = cv_of(p, c, s.y2, s.ye);
+      T = iso ? Tiso : s.E / cv;
+      chem(net, p, s.y2, s.ye, T, s.Td, c, co);
+    }
+#endif
     /* chemistry + energy: (I - h J) du = h f, u = (y_H2, y_e, E/E_ref) */
     {
       real Eref = s.E;
@@ -1073,6 +1093,7 @@ static void li_cell(const orc_network& net, const orc_params& p, const orc_cells
     }
     fl |= renormalise(net, p, c, s, iso, Tiso);
 
+#ifndef ORC_DUST_FIRST
     /* dust, IR and gas-grain exchange (Appendix C) */
     if (dust_on) {
       if (!tight) {
@@ -1085,6 +1106,7 @@ static void li_cell(const orc_network& net, const orc_params& p, const orc_cells
       }
       fl |= dust_floors(p, c, s);
     }
+#endif
 
     ++nsub;
     if (last) break;
