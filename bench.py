@@ -530,8 +530,13 @@ def grid256_leg(args, sfc, W, torch):
                         "an n^-1.5 tail above 1e4, 8 point sources, Z = 1, dust factor 100, "
                         "dt = 10 kyr", cells=n, dt_s=dt)
     res = {}
-    for prec, name in ((sfc.FP64, "fp64"), (sfc.MIXED, "mixed")):
-        ctx = sfc.Context(dust_factor=100.0)
+    # progress dispatch (the default) and density dispatch, whose results are
+    # bitwise the same: this population has few long cells (see DESIGN)
+    for prec, name, disp in ((sfc.FP64, "fp64", None), (sfc.MIXED, "mixed", None),
+                             (sfc.FP64, "fp64_density", sfc.DISPATCH_DENSITY),
+                             (sfc.MIXED, "mixed_density", sfc.DISPATCH_DENSITY)):
+        ctx = sfc.Context(dust_factor=100.0, params=sfc.default_params(dispatch=disp)
+                          if disp is not None else None)
         times = []
         for rep in range(2):
             for k in STATE_KEYS:
@@ -546,11 +551,18 @@ def grid256_leg(args, sfc, W, torch):
             times.append(e0.elapsed_time(e1) * 1e-3)
         ctx.close()
         o = {k: v.cpu().numpy() for k, v in work.items()}
-        res[name] = o
         ns = o["nsub"].astype(np.int64)
         s = times[-1]
         out[name] = dict(value=n / s, seconds=s, nsub=stats(ns),
                          roofline_frac=FLOP_PER_SUBCYCLE * float(ns.sum()) / s / PEAK_FP64_VALU)
+        if disp is None:
+            res[name] = o
+        else:
+            base = res[name.split("_")[0]]
+            out[name]["bitwise_same_as_progress"] = bool(all(
+                np.array_equal(o[k].view(np.int64) if o[k].dtype == np.float64 else o[k],
+                               base[k].view(np.int64) if base[k].dtype == np.float64 else base[k])
+                for k in o))
         log(f"[bench] grid256 {name}: {s:.3f} s, {n / s:.3e} cell-updates/s")
     out["mixed_speedup_vs_fp64"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
     if not args.no_cpu:
