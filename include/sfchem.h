@@ -65,7 +65,10 @@ typedef enum { SFC_DUST_EVOLVE = 0, SFC_DUST_FROZEN = 1 } sfc_dust_mode;
  *             the subcycles still needed at the larger of the cell's average
  *             pace so far and the pace of its last subcycle.  Cells that
  *             cost ~1e5 subcycles then start first instead of wherever
- *             density puts them.  Uses 36 B of context-owned device memory
+ *             density puts them.  On calls of more than two cells per GPU
+ *             lane the first pass suspends only when the cells with n_H >=
+ *             1e6 cm^-3 (the long ones) outnumber the lanes; with fewer it
+ *             runs every cell to its end, as density order does.  Uses 36 B of context-owned device memory
  *             per cell (allocated at the first call that needs more).
  *   NR comparator calls (sfc_chem_step_nr) use DENSITY under PROGRESS. */
 typedef enum {

@@ -519,6 +519,7 @@ int step_launch(sfc_ctx* ctx, const sfc_cells* cells, double dt, int method, voi
   a.order = nullptr;
   a.dense = nullptr;
   a.budget = 0;
+  a.budget_dev = nullptr;
   a.resume = 0;
   a.fine = 0;
   a.limit = nullptr;
@@ -540,7 +541,8 @@ int step_launch(sfc_ctx* ctx, const sfc_cells* cells, double dt, int method, voi
     // (cells of one density share a wave and branch alike); plain density
     // dispatch orders the densest quarter and keeps the rest in index order
     const hipError_t oe = sfk::launch_order(cells->nh, cells->n, progress, buf.order,
-                                            buf.buckets, s);
+                                            buf.buckets, s, int64_t(grid) * sfk::kBlock,
+                                            ctx->phase_nsub);
     if (oe != hipSuccess) return hip_fail(ctx, oe, "dispatch order launch");
     a.order = buf.order;
     a.dense = buf.buckets + sfk::kOrderDenseWord;
@@ -548,6 +550,8 @@ int step_launch(sfc_ctx* ctx, const sfc_cells* cells, double dt, int method, voi
   if (progress) {
     a.sus = buf.sus;
     a.budget = ctx->phase_nsub;
+    // with the density order in place the plan decides on the device
+    if (density) a.budget_dev = buf.buckets + sfk::kOrderBudgetWord;
     const hipError_t re = sfk::launch_reset(a.sus.count, s);
     if (re != hipSuccess) return hip_fail(ctx, re, "reset launch");
   }
@@ -561,6 +565,7 @@ int step_launch(sfc_ctx* ctx, const sfc_cells* cells, double dt, int method, voi
     if (e != hipSuccess) return hip_fail(ctx, e, "progress order launch");
     sfk::Args b = a;
     b.budget = 0;
+    b.budget_dev = nullptr;
     b.resume = 1;
     b.fine = 1;
     b.order = buf.order;

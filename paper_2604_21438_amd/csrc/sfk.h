@@ -88,6 +88,7 @@ struct Args {
   // sus) and the lane takes another cell.  resume: work items are slots of
   // sus, taken through order, and each continues exactly where it stopped.
   int32_t budget;
+  const uint32_t* budget_dev;        // if set, the budget read on the device instead
   int32_t resume;
   int32_t fine;                      // claim per refill only what idle lanes take, everywhere
   const unsigned long long* limit;   // number of work items, on the device (null: c.n)
@@ -113,8 +114,12 @@ constexpr int kOrderBuckets = 128;
 constexpr int kOrderBlocks = 1024;
 constexpr int kOrderWork = 2 * kOrderBuckets + 4 + 2 * kOrderBlocks;
 constexpr int kOrderDenseWord = 2 * kOrderBuckets + 1;  // plan[1]: length of the dense head
+constexpr int kOrderBudgetWord = 2 * kOrderBuckets + 2;  // plan[2]: first-pass budget (progress)
+// With all_dense (the first pass of progress dispatch) the plan also
+// writes the first pass's suspension budget into work[kOrderBudgetWord]:
+// `budget` when at least `lanes` cells have n_H >= 1e6 cm^-3, else 0.
 hipError_t launch_order(const double* nh, int64_t n, bool all_dense, int32_t* order,
-                        uint32_t* work, hipStream_t s);
+                        uint32_t* work, hipStream_t s, int64_t lanes = 0, int32_t budget = 0);
 // Two-phase dispatch, second phase: order[0..*sus.count) = the suspended
 // slots, longest estimated remainder first (cap = slot capacity; each
 // slot's cost bucket was written when its cell was suspended).

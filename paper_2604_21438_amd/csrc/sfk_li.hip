@@ -51,6 +51,8 @@ __device__ __attribute__((always_inline)) inline void step_loop() {
   double tsub = 0.0;  // NR driver state
   int lev = 0, attempts = 0;
   unsigned long long sbase = 0;  // wave-uniform stash: positions [sbase, sbase + sleft)
+  const int32_t budget = kargs<Args>().budget_dev ? int32_t(*kargs<Args>().budget_dev)
+                                                   : kargs<Args>().budget;
   unsigned sleft = 0;
   for (;;) {
     const Args& a = kargs<Args>();
@@ -107,7 +109,7 @@ __device__ __attribute__((always_inline)) inline void step_loop() {
       if (done) {
         store_cell<R>(fresh(a.netc), fresh(a.parc), a.c, cell, L, a.dt);
         cell = -1;
-      } else if (!kNR && a.budget > 0 && L.nsub >= a.budget) {
+      } else if (!kNR && budget > 0 && L.nsub >= budget) {
         // first pass over: one slot counter update per wave
         const unsigned long long m = __ballot(true);
         const int leader = __ffsll((long long)m) - 1;
@@ -189,7 +191,8 @@ __global__ __launch_bounds__(256) void order_count_kernel(const double* nh, int6
 
 // One thread: the cut bucket, the dense buckets' offsets (densest first)
 // and the number of dense cells; all_dense puts every cell in the head.
-__global__ void order_plan_kernel(int64_t n, int all_dense, uint32_t* work) {
+__global__ void order_plan_kernel(int64_t n, int all_dense, int64_t lanes, int32_t budget,
+                                  uint32_t* work) {
   if (threadIdx.x != 0) return;
   const OrderWork w = order_work(work);
   const uint64_t cap = all_dense ? uint64_t(n) : uint64_t(n) / 4;
@@ -207,6 +210,15 @@ __global__ void order_plan_kernel(int64_t n, int all_dense, uint32_t* work) {
   }
   w.plan[0] = uint32_t(cut);
   w.plan[1] = off;
+  if (all_dense) {
+    // Progress dispatch pays off when the long (dense) cells outnumber the
+    // lanes: the resumed pass then starts the longest first.  With fewer,
+    // suspending them at the budget only postpones their rest until the
+    // whole first pass is over, so the first pass runs every cell to its end.
+    uint64_t dense = 0;
+    for (int b = density_bucket(1.0e6); b < kOrderBuckets; ++b) dense += w.hist[b];
+    w.plan[2] = dense >= uint64_t(lanes) ? uint32_t(budget) : 0u;
+  }
 }
 
 __global__ __launch_bounds__(256) void order_blockcount_kernel(const double* nh, int64_t n,
@@ -393,13 +405,14 @@ int max_blocks_per_cu(int precision, bool si) {
 }
 
 hipError_t launch_order(const double* nh, int64_t n, bool all_dense, int32_t* order,
-                        uint32_t* work, hipStream_t s) {
+                        uint32_t* work, hipStream_t s, int64_t lanes, int32_t budget) {
   const int64_t tiles = (n + 255) / 256;
   const int grid = int(tiles < kOrderBlocks ? (tiles > 0 ? tiles : 1) : kOrderBlocks);
   const int64_t chunk = ((tiles + grid - 1) / grid) * 256;
   hipLaunchKernelGGL(order_zero_kernel, dim3(1), dim3(256), 0, s, work);
   hipLaunchKernelGGL(order_count_kernel, dim3(grid), dim3(256), 0, s, nh, n, chunk, work);
-  hipLaunchKernelGGL(order_plan_kernel, dim3(1), dim3(64), 0, s, n, int(all_dense), work);
+  hipLaunchKernelGGL(order_plan_kernel, dim3(1), dim3(64), 0, s, n, int(all_dense), lanes, budget,
+                     work);
   hipLaunchKernelGGL(order_blockcount_kernel, dim3(grid), dim3(256), 0, s, nh, n, chunk, work);
   hipLaunchKernelGGL(order_blockscan_kernel, dim3(1), dim3(64), 0, s, grid, work);
   hipLaunchKernelGGL(order_scatter_kernel, dim3(grid), dim3(256), 0, s, nh, n, chunk, work,

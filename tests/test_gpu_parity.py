@@ -342,6 +342,24 @@ def test_progress_dispatch_modes_bitwise():
         _assert_bitwise(a, b, keys)
 
 
+def test_progress_first_pass_decided_on_the_device():
+    """With the density order in place (more than two cells per lane) the
+    first pass's budget is set on the device: suspension on where the dense
+    cells (n_H >= 1e6) outnumber the lanes (the 128^3 population), off where
+    they are few (a 96^3 draw of the 256^3 recipe).  Either way the result is
+    bitwise that of density dispatch."""
+    sfc = _sfc()
+    big, dt = W.grid128()
+    few, dt2 = W.grid256(side=96)
+    assert np.sum(big["nh"] >= 1e6) > 131072 > 10 * np.sum(few["nh"] >= 1e6)
+    for name, c, d, fac in (("128^3", big, dt, 1.0), ("96^3 of the 256^3 recipe", few, dt2, 100.0)):
+        a = run_gpu(c, d, sfc.FP64, fac, sfc.default_network(),
+                    sfc.default_params(dispatch=sfc.DISPATCH_DENSITY), label=f"{name} density")
+        b = run_gpu(c, d, sfc.FP64, fac, sfc.default_network(),
+                    sfc.default_params(dispatch=sfc.DISPATCH_PROGRESS), label=f"{name} progress")
+        _assert_bitwise(a, b, BITWISE_KEYS + ("eir",))
+
+
 def test_progress_dispatch_edge_cases():
     """Two-phase dispatch at the edges: one cell; a ragged count with invalid
     cells among them (never suspended, marked as with index order); a first
