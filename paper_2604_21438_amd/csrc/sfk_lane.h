@@ -458,6 +458,8 @@ struct CellK {
   double k9, k10, k11;  // photo / CR rates
   double g4;            // photoelectric heating / (k_B n) [K/s] (pe_mode 0), G0 (pe_mode 1)
   double euv;           // dust UV absorption [erg/g/s]
+  double ikn, irho;     // 1 / (k_B n), 1 / rho
+  double rho_kn;        // rho / (k_B n)
 };
 
 // A += s * (k * x), k a function of T only; the accumulator's mask holds x's
@@ -1064,7 +1066,7 @@ __device__ inline void dust_tight(const Net& nt, const Par& pr, Lane& L, double 
   t.h = h;
   t.cd = pr.cd;
   t.euv = L.ck.euv;
-  const double alpha = cv * frcp(L.ck.rho);
+  const double alpha = cv * L.ck.irho;
   t.ggd = double(d.G) * double(d.gd);
   const double w = h * L.ck.fd * t.ggd;
   const double iaw = frcp(alpha + w);
@@ -1140,7 +1142,7 @@ __device__ inline void dust_linear(const Net& nt, const Par& pr, Lane& L, double
   const double ac = ARAD * CL;
   const double G = double(d.G), gd = double(d.gd), zeta = double(d.zeta);
   const double betad = double(d.betad), betair = double(d.betair);
-  const double alpha = cv * frcp(L.ck.rho);
+  const double alpha = cv * L.ck.irho;
   const double td3 = L.Td * L.Td * L.Td;
   const double rho = L.ck.rho, fd = L.ck.fd, cd = pr.cd;
   const double A00 = cd + h * G * gd + h * ac * td3 * betad;
@@ -1192,7 +1194,7 @@ __device__ bool subcycle(const Net& nt, const Par& pr, Lane& L) {
   const bool dust_on = (pr.dust_mode == 0) && !iso;
   const double knb = KB * L.ck.n;
   const double ntr = ntot_rel(pr, L.y2, L.ye);
-  const double Ek = L.E * frcp(knb);            // E_th / (k_B n) [K]
+  const double Ek = L.E * L.ck.ikn;             // E_th / (k_B n) [K]
   const double intr = frcp(ntr);
   const double T = iso ? L.Tiso : Ek * pr.gm1 * intr;
 
@@ -1207,8 +1209,8 @@ __device__ bool subcycle(const Net& nt, const Par& pr, Lane& L) {
     Dust<double> d;
     dust_gas<double>(nt, T, L.Td, L.ck, rad, d);
     // gas-grain exchange rho S_g / (k_B n) [K/s]
-    qgg = double(d.Sg) * (L.ck.rho / knb);
-    const double alpha = knb * (ntr * pr.igm1) * frcp(L.ck.rho);
+    qgg = double(d.Sg) * L.ck.rho_kn;
+    const double alpha = knb * (ntr * pr.igm1) * L.ck.irho;
     // Near radiative equilibrium S_d and S_IR are differences of terms far
     // larger than themselves, known to a few ulps each: a net source within
     // kSrcNoise of its gross terms is rounding noise and sets no timescale
@@ -1514,6 +1516,10 @@ __device__ inline void cell_consts(const Net& nt, const Par& pr, double nh, doub
   k.k11 = nt.rm[11] * nt.zeta;
   k.g4 = nt.pe_mode == 1 ? g0 : nt.pm[3] * nt.pe_k * g0 * z;  // Gamma_4 / (k_B n), or G0
   k.euv = nt.kap_uv_c * (nf * nt.e_fuv + ne * nt.e_euv);
+  const double knb = KB * nh;
+  k.ikn = frcp(knb);
+  k.irho = frcp(k.rho);
+  k.rho_kn = k.rho / knb;
 }
 
 // Two-phase dispatch: write a running cell's state back in place (its
